@@ -1,0 +1,133 @@
+"""Seeded, synthetic inputs shared by the tests, the benchmark and the oracle.
+
+This module holds parameter sets and random draws only: no part of the
+steady-state method's arithmetic lives here, so that the oracle (``oracle/``)
+and the HIP path (``paper_1411_4356_amd``) can both read it without sharing
+any computation.
+
+Every workload is the optomechanical model of Eq. (1) and Eq. (3) at fixed
+parameters in units of the mechanical frequency (omega_m = 1).  There is no
+dataset: the operator is fully determined by its parameters.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import List
+
+import numpy as np
+
+#: Seed for the parameter batch of the 360,000-row workload (E uniform in
+#: [0.1, 0.6]).  Printed by the benchmark so runs can be repeated.
+BATCH_SEED = 14114356
+
+
+@dataclasses.dataclass(frozen=True)
+class ModelParams:
+    """Parameters of Eq. (1) and Eq. (3) plus the Fock truncation.
+
+    nc, nm   -- cavity and mechanical Fock cutoffs (Hilbert dim N = nc*nm).
+    delta    -- pump-cavity detuning Delta.
+    omega_m  -- mechanical frequency (the unit, 1.0).
+    g0       -- single-photon radiation-pressure coupling.
+    E        -- pump amplitude.
+    kappa    -- cavity damping rate.
+    gamma_m  -- mechanical damping rate Gamma_m = omega_m / Q_m.
+    n_th     -- thermal occupation of the mechanical bath.
+    """
+
+    nc: int
+    nm: int
+    delta: float
+    g0: float
+    E: float
+    kappa: float
+    gamma_m: float
+    n_th: float
+    omega_m: float = 1.0
+
+    @property
+    def hilbert_dim(self) -> int:
+        return self.nc * self.nm
+
+    @property
+    def n(self) -> int:
+        return self.hilbert_dim ** 2
+
+    def replace(self, **kw) -> "ModelParams":
+        return dataclasses.replace(self, **kw)
+
+
+@dataclasses.dataclass(frozen=True)
+class SolverOpts:
+    """Solver knobs: ILUT drop tolerance d and fill p (Sec. II), GMRES
+    restart length m and relative-residual tolerance (Sec. IV)."""
+
+    drop_tol: float
+    fill_factor: float
+    restart: int
+    tol: float
+    maxiter: int = 1000
+
+
+# --- the five workloads -----------------------------------------------------
+
+#: Tiny case: 1,600 rows; the oracle solves it densely in well under a second.
+TINY = ModelParams(nc=4, nm=10, delta=1.0, g0=0.6, E=0.2, kappa=0.3,
+                   gamma_m=1e-3, n_th=0.5)
+TINY_OPTS = SolverOpts(drop_tol=1e-5, fill_factor=60.0, restart=50, tol=1e-12)
+
+#: Plain FP64 batch workload: 360,000 rows, eight pump amplitudes.
+BATCH_BASE = ModelParams(nc=10, nm=60, delta=1.0, g0=0.8, E=0.35, kappa=0.4,
+                         gamma_m=1e-3, n_th=1.0)
+BATCH_OPTS = SolverOpts(drop_tol=1e-6, fill_factor=60.0, restart=100, tol=1e-10)
+
+#: Adjoint / gradient workload: 1.44M rows, zero-temperature bath.
+ADJOINT = ModelParams(nc=12, nm=100, delta=1.0, g0=1.0, E=0.4, kappa=0.5,
+                      gamma_m=1e-3, n_th=0.0)
+ADJOINT_OPTS = SolverOpts(drop_tol=1e-6, fill_factor=60.0, restart=100, tol=1e-10)
+
+#: Mixed-precision GMRES-IR workload: 6.55M rows.
+MIXED = ModelParams(nc=16, nm=160, delta=1.0, g0=1.2, E=0.5, kappa=0.5,
+                    gamma_m=1e-3, n_th=0.5)
+MIXED_OPTS = SolverOpts(drop_tol=1e-5, fill_factor=40.0, restart=50, tol=1e-10)
+
+#: Largest single-GPU problem: 25M rows.
+LARGE = ModelParams(nc=20, nm=250, delta=1.0, g0=1.5, E=0.6, kappa=0.6,
+                    gamma_m=1e-3, n_th=0.0)
+LARGE_OPTS = SolverOpts(drop_tol=1e-5, fill_factor=40.0, restart=50, tol=1e-8)
+
+#: Fig. 1 sizes (N_c=4, N_m=8, thermal bath); only the structure matters.
+FIG1 = ModelParams(nc=4, nm=8, delta=1.0, g0=0.5, E=0.1, kappa=0.2,
+                   gamma_m=1e-4, n_th=3.0)
+
+
+def batch_E(count: int = 8, seed: int = BATCH_SEED) -> np.ndarray:
+    """Pump amplitudes of the batch workload: E_b = 0.1 + 0.5 * u_b with
+    u = default_rng(seed).random(count)."""
+    u = np.random.default_rng(seed).random(count)
+    return 0.1 + 0.5 * u
+
+
+def batch_params(base: ModelParams = BATCH_BASE, count: int = 8,
+                 seed: int = BATCH_SEED) -> List[ModelParams]:
+    return [base.replace(E=float(e)) for e in batch_E(count, seed)]
+
+
+def random_complex(n: int, seed: int = 0, count: int | None = None) -> np.ndarray:
+    """Complex standard-normal vector(s) from default_rng(seed): shape (n,)
+    or (count, n), complex128."""
+    rng = np.random.default_rng(seed)
+    shape = (n,) if count is None else (count, n)
+    return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
+def small_cases() -> List[ModelParams]:
+    """Reduced truncations of the five workloads (same physical parameters),
+    small enough for a dense or sparse direct oracle solve in seconds."""
+    return [
+        TINY,
+        BATCH_BASE.replace(nc=4, nm=12),
+        ADJOINT.replace(nc=4, nm=12),
+        MIXED.replace(nc=4, nm=14),
+        LARGE.replace(nc=4, nm=12),
+    ]
