@@ -1,0 +1,132 @@
+"""ctypes declarations of the C ABI in include/omss.h (libomss.so)."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "libomss.so")
+
+OM_OK, OM_EINVAL, OM_ENOMEM, OM_EHIP, OM_ENOTCONV, OM_EBREAKDOWN, OM_ETIMEOUT = range(7)
+STATUS_NAMES = {0: "OM_OK", 1: "OM_EINVAL", 2: "OM_ENOMEM", 3: "OM_EHIP", 4: "OM_ENOTCONV",
+                5: "OM_EBREAKDOWN", 6: "OM_ETIMEOUT"}
+OM_C128, OM_C64 = 0, 1
+OM_TRACE_NONE, OM_TRACE_REPLACE_ROW0, OM_TRACE_ADD_ROW0 = 0, 1, 2
+OM_PREC_FP64, OM_PREC_IR_C64 = 0, 1
+OM_BUILD_C64 = 1
+OM_ILU_C64, OM_ILU_ADJOINT, OM_ILU_CONDEST, OM_ILU_KEEP_HOST = 1, 2, 4, 8
+
+
+class om_params(C.Structure):
+    _fields_ = [("nc", C.c_int32), ("nm", C.c_int32), ("delta", C.c_double), ("omega_m", C.c_double),
+                ("g0", C.c_double), ("E", C.c_double), ("kappa", C.c_double), ("gamma_m", C.c_double),
+                ("n_th", C.c_double)]
+
+
+class om_order_stats(C.Structure):
+    _fields_ = [(k, C.c_int64) for k in ("ub0", "lb0", "B0", "P0", "ub1", "lb1", "B1", "P1")]
+
+
+class om_ilu_stats(C.Structure):
+    _fields_ = [("fill", C.c_double), ("condest", C.c_double), ("nnz_L", C.c_int64), ("nnz_U", C.c_int64),
+                ("depth_L", C.c_int64), ("depth_U", C.c_int64), ("repaired_pivots", C.c_int64),
+                ("t_factor_s", C.c_double)]
+
+
+class om_gmres_opts(C.Structure):
+    _fields_ = [("m", C.c_int32), ("maxiter", C.c_int32), ("precision", C.c_int32), ("max_outer", C.c_int32),
+                ("tol", C.c_double), ("inner_tol", C.c_double)]
+
+
+class om_gmres_info(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("restarts", C.c_int32), ("outer_iters", C.c_int32), ("converged", C.c_int32),
+                ("relres_true", C.c_double), ("relres_est", C.c_double), ("t_spmv_s", C.c_double),
+                ("t_ilu_s", C.c_double), ("t_orth_s", C.c_double), ("t_total_s", C.c_double)]
+
+
+class om_ss_opts(C.Structure):
+    _fields_ = [("drop_tol", C.c_double), ("fill_factor", C.c_double), ("gmres", om_gmres_opts),
+                ("trace_mode", C.c_int32), ("nth0_fix", C.c_int32), ("reorder", C.c_int32),
+                ("want_adjoint", C.c_int32)]
+
+
+class om_ss_info(C.Structure):
+    _fields_ = [("order", om_order_stats), ("ilu", om_ilu_stats), ("gmres", om_gmres_info),
+                ("t_build_s", C.c_double), ("t_rcm_s", C.c_double), ("t_factor_s", C.c_double),
+                ("t_solve_s", C.c_double), ("t_post_s", C.c_double)]
+
+
+_dp = C.POINTER(C.c_double)
+
+
+class om_ss_results(C.Structure):
+    _fields_ = [("trace_err", _dp), ("herm_err", _dp), ("n_a", _dp), ("n_b", _dp), ("fano", _dp), ("relres", _dp)]
+
+
+_P = C.c_void_p
+_i32 = C.c_int32
+_i64 = C.c_int64
+_u32 = C.c_uint32
+_pi64 = C.POINTER(C.c_int64)
+_pi32 = C.POINTER(C.c_int32)
+
+SIGNATURES = {
+    "om_last_error": (C.c_char_p, []),
+    "om_version": (C.c_char_p, []),
+    "liouvillian_build": (C.c_int, [C.POINTER(om_params), _i32, _i32, _u32, C.POINTER(_P), _dp, _P]),
+    "om_csr_info": (C.c_int, [_P, _pi64, _pi64, _pi32, _pi32]),
+    "om_csr_export": (C.c_int, [_P, _pi64, _pi32, _dp, _P]),
+    "rcm_permute": (C.c_int, [_P, _pi32, C.POINTER(_P), C.POINTER(om_order_stats), _P]),
+    "csr_permute": (C.c_int, [_P, _pi32, C.POINTER(_P), _P]),
+    "ilu_factor": (C.c_int, [_P, C.c_double, C.c_double, _u32, C.POINTER(_P), C.POINTER(om_ilu_stats), _P]),
+    "om_ilu_info": (C.c_int, [_P, _i32, _pi64, _pi64, _pi64]),
+    "om_ilu_export": (C.c_int, [_P, _i32, _pi64, _pi32, _dp, _pi64, _pi32, _dp]),
+    "ilu_apply": (C.c_int, [_P, _i32, _i32, _P, _P, _P]),
+    "csr_spmv": (C.c_int, [_P, _i32, _i32, _P, _P, _P]),
+    "gmres_solve": (C.c_int, [_P, _P, _i32, _P, _P, C.POINTER(om_gmres_opts), C.POINTER(om_gmres_info), _P]),
+    "steady_state": (C.c_int, [C.POINTER(om_params), _i32, C.POINTER(om_ss_opts), _P, C.POINTER(om_ss_info),
+                               C.POINTER(om_ss_results), _P]),
+    "om_ss_opts_default": (None, [C.POINTER(om_ss_opts)]),
+    "om_observables": (C.c_int, [_P, _P, _dp, _P]),
+    "om_objective_vectors": (C.c_int, [_P, _P, _P, _P]),
+    "om_param_gradient": (C.c_int, [_P, _P, _P, _i32, _dp, _P]),
+    "om_csr_free": (None, [_P]),
+    "om_ilu_free": (None, [_P]),
+    "om_host_rcm": (C.c_int, [_i64, _pi64, _pi32, _pi32]),
+    "om_host_ilut": (C.c_int, [_i64, _pi64, _pi32, _dp, C.c_double, C.c_double, C.POINTER(_P),
+                               C.POINTER(om_ilu_stats)]),
+}
+
+_lib = None
+
+
+class LibraryMissing(RuntimeError):
+    pass
+
+
+def lib():
+    """Load libomss.so (built in-tree by paper_1411_4356_amd.build).  Raises
+    LibraryMissing if it has not been built: there is no fallback path."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIBPATH):
+            raise LibraryMissing(f"{LIBPATH} is missing: build it with `python -m paper_1411_4356_amd.build`")
+        L = C.CDLL(LIBPATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+class OmError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+def check(status: int, allow=()):
+    if status != OM_OK and status not in allow:
+        raise OmError(status, lib().om_last_error().decode(errors="replace"))
+    return status

@@ -1,0 +1,165 @@
+// Internal definitions shared by the host and device sources of libomss.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/omss.h"
+
+namespace omss {
+
+// ---- error state (thread-local message, see om_last_error) -------------------
+void set_error(const char* fmt, ...) __attribute__((format(printf, 1, 2)));
+const char* last_error();
+
+#define OM_HIP(expr)                                                                \
+    do {                                                                            \
+        hipError_t e__ = (expr);                                                    \
+        if (e__ != hipSuccess) {                                                    \
+            ::omss::set_error("%s:%d: %s failed: %s", __FILE__, __LINE__, #expr,     \
+                              hipGetErrorString(e__));                              \
+            return e__ == hipErrorOutOfMemory ? OM_ENOMEM : OM_EHIP;                \
+        }                                                                           \
+    } while (0)
+
+#define OM_TRY(expr)                         \
+    do {                                     \
+        om_status s__ = (expr);              \
+        if (s__ != OM_OK) return s__;        \
+    } while (0)
+
+// ---- device buffer ------------------------------------------------------------
+template <typename T>
+struct DevBuf {
+    T* p = nullptr;
+    size_t n = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+    DevBuf& operator=(DevBuf&& o) noexcept {
+        if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+        return *this;
+    }
+    ~DevBuf() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    om_status alloc(size_t count) {
+        release();
+        if (count == 0) return OM_OK;
+        hipError_t e = hipMalloc((void**)&p, count * sizeof(T));
+        if (e != hipSuccess) {
+            p = nullptr;
+            set_error("hipMalloc of %zu bytes failed: %s", count * sizeof(T), hipGetErrorString(e));
+            return OM_ENOMEM;
+        }
+        n = count;
+        return OM_OK;
+    }
+    om_status upload(const T* host, size_t count, hipStream_t s) {
+        OM_TRY(alloc(count));
+        if (count) OM_HIP(hipMemcpyAsync(p, host, count * sizeof(T), hipMemcpyHostToDevice, s));
+        return OM_OK;
+    }
+    size_t bytes() const { return n * sizeof(T); }
+};
+
+inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// Grid size helper.
+inline unsigned blocks_for(int64_t work, int per_block) {
+    int64_t b = (work + per_block - 1) / per_block;
+    return (unsigned)(b < 1 ? 1 : b);
+}
+
+}  // namespace omss
+
+// ---- handle types ---------------------------------------------------------------
+
+struct om_csr {
+    int64_t n = 0, nnz = 0;
+    int32_t batch = 1;
+    int32_t N = 0;                       // Hilbert dimension (0 if no model)
+    omss::DevBuf<int32_t> row_ptr, col;  // pattern (shared by the batch)
+    omss::DevBuf<double2> val;           // batch * nnz
+    omss::DevBuf<float2> val32;          // optional complex64 copy
+    // conjugate transpose, built on demand for A^H products
+    bool has_t = false;
+    omss::DevBuf<int32_t> t_row_ptr, t_col, t_src;
+    omss::DevBuf<double2> t_val;
+    omss::DevBuf<float2> t_val32;
+    // host copy of the pattern (row_ptr as int64), built on demand
+    std::vector<int64_t> h_row_ptr;
+    std::vector<int32_t> h_col;
+    // model description
+    bool has_model = false;
+    std::vector<om_params> params;
+    int32_t trace_mode = OM_TRACE_REPLACE_ROW0;
+    std::vector<double> w;
+    // ordering: perm[new] = old relative to the natural model ordering
+    bool permuted = false;
+    std::vector<int32_t> perm;
+    omss::DevBuf<int32_t> perm_d, iperm_d;
+};
+
+namespace omss {
+
+struct HostFactor;
+
+// One unit-lower triangular solve in "solve coordinates" (an upper factor is
+// stored row- and column-reversed so that it is lower triangular too).
+// Rows are grouped in blocks of 64 (one wavefront).  For every block:
+//   - the entries left of the block are stored slot-major (ELL): slot s of
+//     row r at [(off[g] + s) * 64 + r], padded with column 0 / value 0;
+//   - the strictly-lower 64x64 diagonal block is stored packed by column:
+//     column c holds rows c+1..63 at [g * 2016 + c*63 - c*(c-1)/2 + (r-c-1)].
+// dinv (optional): per-row factor applied to the right-hand side (the
+// inverse pivots of U, whose rows are stored scaled to unit diagonal).
+struct TriSched {
+    int64_t n = 0, nblk = 0, nslots = 0;
+    bool rev = false;
+    int64_t depth = 0;
+    DevBuf<int64_t> off;
+    DevBuf<int32_t> col;
+    DevBuf<double2> val;
+    DevBuf<float2> val32;
+    DevBuf<double2> dg;
+    DevBuf<float2> dg32;
+    DevBuf<double2> dinv;
+    DevBuf<float2> dinv32;
+};
+
+// POD view of a TriSched for kernels.
+template <typename VT>
+struct TriView {
+    const int64_t* off;
+    const int32_t* col;
+    const VT* val;
+    const VT* dg;
+    const VT* dinv;   // may be null
+    int64_t n, nblk;
+    int32_t rev;
+};
+
+}  // namespace omss
+
+struct om_ilu {
+    int64_t n = 0;
+    int32_t batch = 0;
+    uint32_t flags = 0;
+    bool host_only = false;
+    std::vector<std::unique_ptr<omss::HostFactor>> host;   // per batch item
+    // per batch item: 0 = L, 1 = U (reversed, scaled), 2 = U^H (scaled), 3 = L^H (reversed)
+    std::vector<omss::TriSched> sched;                     // batch * 4
+    omss::DevBuf<omss::TriView<double2>> views64;          // batch * 4
+    omss::DevBuf<omss::TriView<float2>> views32;           // batch * 4
+    om_ilu_stats stats{};
+};

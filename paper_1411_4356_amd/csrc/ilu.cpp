@@ -1,0 +1,160 @@
+// ilu_factor: host ILUT of every batch item (one host thread per item), solve
+// schedules, upload of the factors to the device.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <mutex>
+#include <thread>
+
+#include "common.hpp"
+#include "ilu.hpp"
+#include "ilut.hpp"
+#include "kernels.hpp"
+#include "ordering.hpp"
+#include "schedule.hpp"
+
+namespace omss {
+
+static om_status finish_views(om_ilu* M, hipStream_t s) {
+    const int B = M->batch;
+    std::vector<TriView<double2>> v64((size_t)B * 4);
+    std::vector<TriView<float2>> v32((size_t)B * 4);
+    for (int b = 0; b < B; ++b)
+        for (int k = 0; k < 4; ++k) {
+            const TriSched& S = M->sched[(size_t)b * 4 + k];
+            TriView<double2>& a = v64[(size_t)b * 4 + k];
+            a.off = S.off.p; a.col = S.col.p; a.val = S.val.p; a.dg = S.dg.p; a.dinv = S.dinv.p;
+            a.n = S.n; a.nblk = S.nblk; a.rev = S.rev;
+            TriView<float2>& c = v32[(size_t)b * 4 + k];
+            c.off = S.off.p; c.col = S.col.p; c.val = S.val32.p; c.dg = S.dg32.p; c.dinv = S.dinv32.p;
+            c.n = S.n; c.nblk = S.nblk; c.rev = S.rev;
+        }
+    OM_TRY(M->views64.upload(v64.data(), v64.size(), s));
+    OM_TRY(M->views32.upload(v32.data(), v32.size(), s));
+    OM_HIP(hipStreamSynchronize(s));
+    return OM_OK;
+}
+
+om_status ilu_factor_impl(const om_csr* Ain, double drop_tol, double fill_factor, uint32_t flags, om_ilu** M_out,
+                          om_ilu_stats* st, hipStream_t s) {
+    if (!(drop_tol >= 0.0) || !(fill_factor > 0.0)) {
+        set_error("drop_tol must be >= 0 and fill_factor > 0 (got %g, %g)", drop_tol, fill_factor);
+        return OM_EINVAL;
+    }
+    om_csr* A = const_cast<om_csr*>(Ain);
+    const auto t0 = std::chrono::steady_clock::now();
+    OM_TRY(ensure_host_pattern(A, s));
+    const int64_t n = A->n, nnz = A->nnz;
+    const int B = A->batch;
+    std::vector<double> vals((size_t)B * nnz * 2);
+    OM_HIP(hipMemcpyAsync(vals.data(), A->val.p, vals.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    OM_HIP(hipStreamSynchronize(s));
+
+    std::unique_ptr<om_ilu> M(new om_ilu);
+    M->n = n;
+    M->batch = B;
+    M->flags = flags;
+    M->sched.resize((size_t)B * 4);
+    M->host.resize(B);
+    int dev = 0;
+    OM_HIP(hipGetDevice(&dev));
+    const bool adjoint = flags & OM_ILU_ADJOINT;
+    const bool c64 = flags & OM_ILU_C64;
+    std::vector<om_status> status(B, OM_OK);
+    std::vector<std::string> errs(B);
+    std::vector<int64_t> nl(B), nu(B), dl(B), du(B), rep(B);
+    const int T = std::max(1, std::min(B, host_threads()));
+    auto work = [&](int t) {
+        (void)hipSetDevice(dev);
+        for (int b = t; b < B; b += T) {
+            std::unique_ptr<HostFactor> F(new HostFactor);
+            std::string err;
+            ilut_factor_host(n, A->h_row_ptr.data(), A->h_col.data(), vals.data() + (size_t)b * nnz * 2, drop_tol,
+                             fill_factor, F.get(), &err);
+            nl[b] = (int64_t)F->l_col.size();
+            nu[b] = (int64_t)F->u_col.size();
+            rep[b] = F->repaired;
+            for (int k = 0; k < (adjoint ? 4 : 2); ++k) {
+                SolveCSR S;
+                factor_to_solve(*F, k, S);
+                HostTri H;
+                build_host_tri(S, H);
+                S = SolveCSR();
+                if (k == 0) dl[b] = H.depth;
+                if (k == 1) du[b] = H.depth;
+                om_status rc = upload_tri(H, c64, M->sched[(size_t)b * 4 + k]);
+                if (rc != OM_OK) { status[b] = rc; errs[b] = last_error(); return; }
+            }
+            if (flags & OM_ILU_KEEP_HOST) M->host[b] = std::move(F);
+        }
+    };
+    std::vector<std::thread> th;
+    for (int t = 1; t < T; ++t) th.emplace_back(work, t);
+    work(0);
+    for (auto& x : th) x.join();
+    for (int b = 0; b < B; ++b)
+        if (status[b] != OM_OK) { set_error("%s", errs[b].c_str()); return status[b]; }
+    OM_TRY(finish_views(M.get(), s));
+
+    om_ilu_stats S{};
+    for (int b = 0; b < B; ++b) {
+        S.fill = std::max(S.fill, (double)(nl[b] + nu[b]) / (double)nnz);
+        S.nnz_L += nl[b];
+        S.nnz_U += nu[b];
+        S.depth_L = std::max(S.depth_L, dl[b]);
+        S.depth_U = std::max(S.depth_U, du[b]);
+        S.repaired_pivots += rep[b];
+    }
+    S.t_factor_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (flags & OM_ILU_CONDEST) {
+        DevBuf<double2> e;
+        OM_TRY(e.alloc((size_t)B * n));
+        std::vector<double2> ones((size_t)B * n, make_double2(1.0, 0.0));
+        OM_HIP(hipMemcpyAsync(e.p, ones.data(), ones.size() * sizeof(double2), hipMemcpyHostToDevice, s));
+        OM_TRY(ilu_apply_dev(M.get(), 0, OM_C128, e.p, e.p, nullptr, s));
+        OM_HIP(hipMemcpyAsync(ones.data(), e.p, ones.size() * sizeof(double2), hipMemcpyDeviceToHost, s));
+        OM_HIP(hipStreamSynchronize(s));
+        double c = 0;
+        for (const double2& v : ones) c = std::max(c, std::sqrt(v.x * v.x + v.y * v.y));
+        S.condest = c;
+    }
+    M->stats = S;
+    if (st) *st = S;
+    *M_out = M.release();
+    return OM_OK;
+}
+
+om_status host_ilut_impl(int64_t n, const int64_t* row_ptr, const int32_t* col, const double* val, double drop_tol,
+                         double fill_factor, om_ilu** M_out, om_ilu_stats* st) {
+    if (!(drop_tol >= 0.0) || !(fill_factor > 0.0)) {
+        set_error("drop_tol must be >= 0 and fill_factor > 0");
+        return OM_EINVAL;
+    }
+    if (n < 1 || !row_ptr || !col || !val) { set_error("invalid CSR"); return OM_EINVAL; }
+    const auto t0 = std::chrono::steady_clock::now();
+    std::unique_ptr<om_ilu> M(new om_ilu);
+    M->n = n;
+    M->batch = 1;
+    M->host_only = true;
+    M->host.resize(1);
+    M->host[0].reset(new HostFactor);
+    std::string err;
+    ilut_factor_host(n, row_ptr, col, val, drop_tol, fill_factor, M->host[0].get(), &err);
+    const HostFactor& F = *M->host[0];
+    om_ilu_stats S{};
+    S.nnz_L = (int64_t)F.l_col.size();
+    S.nnz_U = (int64_t)F.u_col.size();
+    S.fill = (double)(S.nnz_L + S.nnz_U) / (double)row_ptr[n];
+    S.repaired_pivots = F.repaired;
+    S.depth_L = level_depth(n, F.l_ptr, F.l_col);
+    SolveCSR T;
+    factor_to_solve(F, 1, T);
+    S.depth_U = level_depth(n, T.ptr, T.col);
+    S.t_factor_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    M->stats = S;
+    if (st) *st = S;
+    *M_out = M.release();
+    return OM_OK;
+}
+
+}  // namespace omss

@@ -1,0 +1,22 @@
+// Host ILUT factor container and entry (internal).
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace omss {
+
+struct HostFactor {
+    int64_t n = 0;
+    std::vector<int64_t> l_ptr, u_ptr;
+    std::vector<int32_t> l_col, u_col;
+    std::vector<double> l_val, u_val;   // interleaved re, im
+    int64_t repaired = 0;
+};
+
+// Factor the n x n CSR matrix (values interleaved re,im; columns sorted per
+// row).  Returns 0 on success.
+int ilut_factor_host(int64_t n, const int64_t* row_ptr, const int32_t* col, const double* val,
+                     double drop_tol, double fill_factor, HostFactor* out, std::string* err);
+
+}  // namespace omss

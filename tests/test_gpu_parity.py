@@ -1,0 +1,253 @@
+"""GPU parity of every step of the hot path against the oracle, through the
+C ABI: assembly (Eq. (3)-(5)), RCM (Sec. III), SpMV, ILUT factors and their
+application (Sec. II), GMRES and the steady state (Sec. IV), mixed
+precision and adjoint gradients.  Sizes span several 64-row blocks and a
+ragged tail."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import torch
+
+import workloads as W
+from gpu_util import announce, require_gpu, to_dev, to_host
+from oracle import adjoint as oadj
+from oracle import direct, model, ordering
+from oracle import ilut as oilut
+
+pytestmark = pytest.mark.gpu
+
+import paper_1411_4356_amd as P  # noqa: E402
+
+
+@pytest.fixture(autouse=True)
+def _gpu(request):
+    require_gpu()
+    announce(request.node.nodeid)
+
+
+# n = 441, 1296 (ragged: not a multiple of 64), 1600, and n_th = 0
+CASES = [W.TINY.replace(nc=3, nm=7), W.TINY.replace(nc=4, nm=9), W.TINY, W.ADJOINT.replace(nc=3, nm=8)]
+
+
+def _oracle_system(p, mode=model.TRACE_REPLACE):
+    return model.constrained_system(model.liouvillian(p), mode)
+
+
+@pytest.mark.parametrize("mode", [model.TRACE_NONE, model.TRACE_REPLACE, model.TRACE_ADD])
+@pytest.mark.parametrize("ci", range(len(CASES)))
+def test_build_matches_oracle(ci, mode):
+    p = CASES[ci]
+    Lt, _, w = _oracle_system(p, mode)
+    A, wd = P.liouvillian_build(p, trace_mode=mode)
+    rp, col, val = A.export()
+    assert np.array_equal(rp, Lt.indptr) and np.array_equal(col, Lt.indices)
+    assert np.max(np.abs(val[0] - Lt.data)) <= 1e-14 * np.abs(Lt.data).max()
+    assert abs(wd[0] - w) <= 1e-14 * abs(w)
+
+
+def test_build_batch_matches_oracle_per_item():
+    ps = [W.TINY.replace(nc=3, nm=7, E=e) for e in (0.1, 0.35, 0.6)]
+    A, w = P.liouvillian_build(ps)
+    rp, col, val = A.export()
+    for b, p in enumerate(ps):
+        Lt, _, wo = _oracle_system(p)
+        assert np.array_equal(col, Lt.indices)
+        assert np.max(np.abs(val[b] - Lt.data)) <= 1e-14 * np.abs(Lt.data).max()
+
+
+def test_build_fig1_count():
+    A, _ = P.liouvillian_build(W.FIG1, trace_mode=model.TRACE_ADD)
+    assert A.nnz == 8957
+
+
+@pytest.mark.parametrize("ci", range(len(CASES)))
+def test_rcm_permute_matches_oracle(ci):
+    p = CASES[ci]
+    Lt, _, _ = _oracle_system(p)
+    A, _ = P.liouvillian_build(p)
+    B, perm, st = P.rcm_permute(A)
+    po = ordering.rcm(Lt)
+    assert np.array_equal(perm, po)
+    Bo = ordering.permute(Lt, po)
+    rp, col, val = B.export()
+    assert np.array_equal(rp, Bo.indptr) and np.array_equal(col, Bo.indices)
+    assert np.max(np.abs(val[0] - Bo.data)) <= 1e-14 * np.abs(Bo.data).max()
+    s0, s1 = ordering.bandwidth_profile(Lt), ordering.bandwidth_profile(Bo)
+    assert (st["B0"], st["P0"], st["B1"], st["P1"]) == (s0["B"], s0["P"], s1["B"], s1["P"])
+    assert (st["ub1"], st["lb1"]) == (s1["ub"], s1["lb"])
+
+
+@pytest.mark.parametrize("adjoint", [0, 1])
+@pytest.mark.parametrize("ci", range(len(CASES)))
+def test_spmv_matches_oracle(ci, adjoint):
+    p = CASES[ci]
+    ps = [p, p.replace(E=p.E * 1.5)]
+    A, _ = P.liouvillian_build(ps, c64=True)
+    B, perm, _ = P.rcm_permute(A)
+    X = W.random_complex(B.n, seed=11, count=2)
+    y = to_host(P.csr_spmv(B, to_dev(X), adjoint=bool(adjoint)))
+    y32 = to_host(P.csr_spmv(B, to_dev(X, torch.complex64), adjoint=bool(adjoint)))
+    for b, q in enumerate(ps):
+        Lt, _, _ = _oracle_system(q)
+        Bo = ordering.permute(Lt, perm)
+        M = Bo.conj().T.tocsr() if adjoint else Bo
+        ref = M @ X[b]
+        bound = abs(M) @ np.abs(X[b])
+        assert np.all(np.abs(y[b] - ref) <= 1e-14 * bound + 1e-300)
+        assert np.all(np.abs(y32[b] - ref) <= 2e-6 * bound)
+
+
+def _factored(p, d, fill, **kw):
+    A, _ = P.liouvillian_build(p)
+    B, perm, _ = P.rcm_permute(A)
+    M = P.ilu_factor(B, d, fill, keep_host=True, **kw)
+    return A, B, perm, M
+
+
+@pytest.mark.parametrize("ci", range(len(CASES)))
+def test_ilu_factor_and_apply_match_oracle(ci):
+    p = CASES[ci]
+    A, B, perm, M = _factored(p, 1e-5, 60.0, adjoint=True, c64=True, condest=True)
+    Lt, _, _ = _oracle_system(p)
+    Bo = ordering.permute(Lt, perm)
+    Lo, Uo, so = oilut.ilut(Bo, 1e-5, 60.0)
+    Lf, Uf = M.export(0)
+    for X, Y in ((Lf, Lo), (Uf, Uo)):
+        assert np.array_equal(X.indptr, Y.indptr) and np.array_equal(X.indices, Y.indices)
+    assert M.stats["nnz_L"] == so["nnz_L"] and M.stats["nnz_U"] == so["nnz_U"]
+    x = W.random_complex(B.n, seed=5)
+    for adj in (False, True):
+        y = to_host(P.ilu_apply(M, to_dev(x[None, :]), adjoint=adj))[0]
+        ref = oilut.apply(Lf, Uf, x, adjoint=adj)
+        ref_o = oilut.apply(Lo, Uo, x, adjoint=adj)
+        assert np.linalg.norm(y - ref) <= 1e-12 * np.linalg.norm(ref)
+        assert np.linalg.norm(y - ref_o) <= 1e-10 * np.linalg.norm(ref_o)
+        y32 = to_host(P.ilu_apply(M, to_dev(x[None, :], torch.complex64), adjoint=adj))[0]
+        assert np.linalg.norm(y32 - ref) <= 1e-3 * np.linalg.norm(ref)
+    assert abs(M.stats["condest"] - oilut.condest(Lo, Uo)) <= 1e-9 * oilut.condest(Lo, Uo)
+
+
+def test_ilu_apply_in_place_and_batched():
+    ps = [W.TINY.replace(nc=4, nm=9, E=e) for e in (0.15, 0.45)]
+    A, B, perm, M = _factored(ps, 1e-5, 60.0)
+    X = W.random_complex(B.n, seed=9, count=2)
+    t = to_dev(X)
+    P.ilu_apply(M, t, t)
+    y = to_host(t)
+    for b in range(2):
+        Lf, Uf = M.export(b)
+        ref = oilut.apply(Lf, Uf, X[b])
+        assert np.linalg.norm(y[b] - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+def test_complete_lu_solves_exactly():
+    """d = 0, no fill cap: the factors are the complete LU (Sec. II), so one
+    preconditioner application solves the system."""
+    p = CASES[0]
+    A, B, perm, M = _factored(p, 0.0, float("inf"))
+    Lt, b, _ = _oracle_system(p)
+    xo = direct.solve(Lt, b)
+    y = to_host(P.ilu_apply(M, to_dev(b[perm][None, :])))[0]
+    assert np.max(np.abs(y - xo[perm])) <= 1e-9 * np.max(np.abs(xo))
+
+
+@pytest.mark.parametrize("ci", range(len(CASES)))
+def test_gmres_solve_matches_direct(ci):
+    p = CASES[ci].replace(n_th=max(CASES[ci].n_th, 1e-15))
+    A, B, perm, M = _factored(p, 1e-5, 60.0)
+    Lt, b, _ = _oracle_system(p)
+    xo = direct.solve(Lt, b)
+    bt = to_dev(b[perm][None, :])
+    x, info = P.gmres_solve(B, M, bt, m=50, tol=1e-12)
+    xs = np.empty_like(xo)
+    xs[perm] = to_host(x)[0]
+    assert info["relres_true"] <= 1e-12
+    assert direct.relative_residual(Lt, b, xs) <= 1e-11
+    assert np.max(np.abs(xs - xo)) <= 1e-9 * np.max(np.abs(xo))
+
+
+def test_gmres_without_preconditioner_and_adjoint():
+    p = CASES[0]
+    A, B, perm, M = _factored(p, 1e-5, 60.0, adjoint=True)
+    Lt, b, _ = _oracle_system(p)
+    Bo = ordering.permute(Lt, perm)
+    g = W.random_complex(B.n, seed=3)
+    lam, info = P.gmres_solve(B, M, to_dev(g[None, :]), adjoint=True, m=50, tol=1e-12)
+    ref = np.linalg.solve(Bo.conj().T.toarray(), g)
+    assert np.max(np.abs(to_host(lam)[0] - ref)) <= 1e-9 * np.max(np.abs(ref))
+    x, info = P.gmres_solve(B, None, to_dev(b[perm][None, :]), m=100, tol=1e-8, maxiter=3000, allow_notconv=True)
+    assert info["iters"] > 0
+
+
+def test_gmres_reports_nonconvergence():
+    p = CASES[1]
+    A, B, perm, M = _factored(p, 1e-2, 2.0)
+    Lt, b, _ = _oracle_system(p)
+    x, info = P.gmres_solve(B, M, to_dev(b[perm][None, :]), m=5, tol=1e-30, maxiter=7, allow_notconv=True)
+    assert info["status"] == "OM_ENOTCONV" and info["iters"] <= 7 + 5
+    with pytest.raises(P.OmError):
+        P.gmres_solve(B, M, to_dev(b[perm][None, :]), m=5, tol=1e-30, maxiter=7)
+
+
+@pytest.mark.parametrize("ci", range(len(W.small_cases())))
+def test_steady_state_matches_oracle(ci):
+    p = W.small_cases()[ci]
+    rho, info, res = P.steady_state(p, drop_tol=1e-5, fill_factor=60.0, m=50, tol=1e-12)
+    rho = to_host(rho)[0]
+    ro, oo = direct.steady_state(p)
+    assert info["gmres"]["relres_true"] <= 1e-12
+    err = np.max(np.abs(rho - ro))
+    assert err <= 1e-9, err
+    assert abs(res["n_a"][0] - oo["n_a"]) <= 1e-9 * max(1.0, abs(oo["n_a"]))
+    assert abs(res["n_b"][0] - oo["n_b"]) <= 1e-9 * max(1.0, abs(oo["n_b"]))
+    assert abs(res["fano"][0] - oo["fano"]) <= 1e-8 * max(1.0, abs(oo["fano"]))
+    assert res["herm_err"][0] <= 1e-9 and res["trace_err"][0] <= 1e-9
+
+
+def test_steady_state_batch_of_pump_amplitudes():
+    ps = [W.BATCH_BASE.replace(nc=4, nm=9, E=e) for e in W.batch_E(4)]
+    rho, info, res = P.steady_state(ps, drop_tol=1e-6, fill_factor=60.0, m=50, tol=1e-11)
+    rho = to_host(rho)
+    for b, p in enumerate(ps):
+        ro, oo = direct.steady_state(p)
+        assert np.max(np.abs(rho[b] - ro)) <= 1e-8
+        assert abs(res["n_b"][b] - oo["n_b"]) <= 1e-8 * oo["n_b"]
+
+
+def test_mixed_precision_matches_fp64():
+    p = W.MIXED.replace(nc=4, nm=12)
+    rho64, i64, r64 = P.steady_state(p, drop_tol=1e-5, fill_factor=60.0, m=30, tol=1e-10)
+    rho32, i32, r32 = P.steady_state(p, drop_tol=1e-5, fill_factor=60.0, m=30, tol=1e-10, precision="ir_c64",
+                                     inner_tol=1e-5)
+    ro, oo = direct.steady_state(p)
+    assert i32["gmres"]["relres_true"] <= 1e-10 and i32["gmres"]["outer_iters"] >= 1
+    assert np.max(np.abs(to_host(rho32)[0] - ro)) <= 1e-8
+    assert abs(r32["n_b"][0] - oo["n_b"]) <= 1e-8 * oo["n_b"]
+
+
+def test_adjoint_gradients_match_oracle():
+    p = W.ADJOINT.replace(nc=3, nm=6, n_th=1e-15)
+    A, _ = P.liouvillian_build(p)
+    B, perm, _ = P.rcm_permute(A)
+    M = P.ilu_factor(B, 1e-8, 100.0, adjoint=True)
+    Lt, b, _ = _oracle_system(p)
+    x, _ = P.gmres_solve(B, M, to_dev(b[perm][None, :]), m=50, tol=1e-14)
+    obs = P.observables(B, x)[0]
+    g = P.objective_vectors(B, x)
+    lam = torch.empty_like(g)
+    for f in range(3):
+        lam[f], _ = P.gmres_solve(B, M, g[f].contiguous(), adjoint=True, m=50, tol=1e-14)
+    grad = P.param_gradient(B, x, lam)[0]
+    vals, go = oadj.gradients(p)
+    assert np.max(np.abs(obs - vals) / np.abs(vals)) <= 1e-10
+    scale = np.maximum(np.abs(go), 1e-6 * np.abs(go).max(axis=1, keepdims=True))
+    assert np.max(np.abs(grad - go) / scale) <= 1e-7
+
+
+def test_invalid_parameters_are_rejected():
+    with pytest.raises(P.OmError):
+        P.liouvillian_build(W.TINY.replace(kappa=-1.0))
+    with pytest.raises(P.OmError):
+        P.liouvillian_build(W.TINY.replace(E=float("nan")))
+    with pytest.raises(P.OmError):
+        P.liouvillian_build(W.TINY.replace(nc=1))
