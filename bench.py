@@ -1,0 +1,191 @@
+#!/usr/bin/env python3
+"""Steady-state throughput benchmark on one MI355X.
+
+Workload (default): the plain-FP64 batch of the 360,000-row operator -- N_c =
+10, N_m = 60 (Hilbert dim 600), Delta = 1, g0 = 0.8, kappa = 0.4,
+Gamma_m = 1e-3, n_th = 1, eight pump amplitudes E uniform in [0.1, 0.6]
+(seeded); RCM, ILUT with drop tolerance 1e-6, GMRES(100) to a relative
+residual of 1e-10.  One step is the whole method for the batch: device
+assembly, RCM, ILUT factorisation, preconditioned GMRES and post-processing
+(liouvillian_build -> rcm_permute -> ilu_factor -> gmres_solve -> rho).
+
+Prints one JSON line: whole-job solves/s, the roofline of the dominant kernel
+(the triangular solves of the preconditioner) from HIP events recorded on its
+launch stream over the timed region, and the oracle timed on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes as C
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    # name: (description, params factory, opts)
+    "batch360k": "N_c=10, N_m=60 (n=360,000), batch of 8 pump amplitudes, FP64, ILUT d=1e-6, GMRES(100), tol 1e-10",
+    "tiny1600": "N_c=4, N_m=10 (n=1,600), one solve, FP64, ILUT d=1e-5, GMRES(50), tol 1e-12",
+}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def make_workload(name, fill):
+    import workloads as W
+    if name == "batch360k":
+        opts = dict(drop_tol=W.BATCH_OPTS.drop_tol, fill_factor=fill or W.BATCH_OPTS.fill_factor,
+                    m=W.BATCH_OPTS.restart, tol=W.BATCH_OPTS.tol, maxiter=W.BATCH_OPTS.maxiter)
+        return W.batch_params(), opts
+    if name == "tiny1600":
+        opts = dict(drop_tol=W.TINY_OPTS.drop_tol, fill_factor=fill or W.TINY_OPTS.fill_factor,
+                    m=W.TINY_OPTS.restart, tol=W.TINY_OPTS.tol, maxiter=W.TINY_OPTS.maxiter)
+        return [W.TINY], opts
+    raise SystemExit(f"unknown workload {name}")
+
+
+def profile_query(lib, cls):
+    launches, ms, nbytes = C.c_int64(), C.c_double(), C.c_double()
+    lib.om_profile_query(cls.encode(), C.byref(launches), C.byref(ms), C.byref(nbytes))
+    return launches.value, ms.value, nbytes.value
+
+
+def cpu_baseline(params, opts, budget_s):
+    """The oracle (direct sparse LU of the constrained system, complex128) on
+    the host, on as many batch items as fit the budget (at least one)."""
+    import numpy as np
+
+    from oracle import direct, model
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([t.get("num_threads", 1) for t in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    t0 = time.perf_counter()
+    done = 0
+    for p in params:
+        L = model.liouvillian(p)
+        Lt, b, _ = model.constrained_system(L)
+        x = direct.solve(Lt, b)
+        assert np.isfinite(x).all()
+        done += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": done / dt, "unit": "solves/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{done} of {len(params)} batch items: Kronecker build + sparse direct LU (scipy splu, "
+                      f"COLAMD) of the constrained system, {dt:.1f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--workload", default="batch360k", choices=sorted(WORKLOADS))
+    ap.add_argument("--fill", type=float, default=None, help="ILUT fill limit p (default: workload's)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "
+              "(no multi-GPU path: the batch items would shard one per GPU, see the design notes).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1411_4356_amd as P
+    lib = P.lib()
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a HIP device")
+    torch.cuda.set_device(0)
+    params, opts = make_workload(args.workload, args.fill)
+    batch = len(params)
+    log(f"workload {args.workload}: {WORKLOADS[args.workload]}; fill p = {opts['fill_factor']}; "
+        f"E = {[round(p.E, 6) for p in params]}")
+
+    def step():
+        rho, info, res = P.steady_state(params, **opts)
+        return info, res
+
+    for w in range(args.warmup):
+        info, _ = step()
+        log(f"warmup {w}: {json.dumps(info['gmres'])}")
+    torch.cuda.synchronize()
+    lib.om_profile_enable(1)
+    lib.om_profile_reset()
+    infos = []
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        info, res = step()
+        infos.append((info, res))
+        log(f"step {k}: build {info['t_build_s']:.3f}s rcm {info['t_rcm_s']:.3f}s factor {info['t_factor_s']:.3f}s "
+            f"solve {info['t_solve_s']:.3f}s post {info['t_post_s']:.3f}s iters {info['gmres']['iters']} "
+            f"relres {info['gmres']['relres_true']:.2e} fill {info['ilu']['fill']:.1f}")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    lib.om_profile_enable(0)
+    elapsed = t1 - t0
+    value = batch * args.steps / elapsed
+
+    trs = profile_query(lib, "trsv")
+    spm = profile_query(lib, "spmv")
+    orth = profile_query(lib, "orth")
+
+    def rate(q):
+        n, ms, b = q
+        if n == 0 or ms <= 0:
+            return None, None
+        return (b / n) / ((ms / n) * 1e-3) / 1e9, ms / n
+
+    trs_gbs, trs_ms = rate(trs)
+    spm_gbs, spm_ms = rate(spm)
+    orth_gbs, orth_ms = rate(orth)
+    solve_s = sum(i["t_solve_s"] for i, _ in infos) / len(infos)
+    factor_s = sum(i["t_factor_s"] for i, _ in infos) / len(infos)
+    last, lres = infos[-1]
+    out = {
+        "metric": "steady-state solves/s (whole method: build+RCM+ILUT+GMRES), FP64, 1e-10 relative residual",
+        "value": value,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c128",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "description": WORKLOADS[args.workload], "batch": batch,
+                   "n": int(params[0].n), "drop_tol": opts["drop_tol"],
+                   "fill_factor": opts["fill_factor"], "restart": opts["m"], "tol": opts["tol"]},
+        "roofline": {"bound": "hbm", "kernel": "trsv_block_kernel (ILU apply, one triangular solve per launch)",
+                     "achieved": trs_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": (trs_gbs / HBM_PEAK_GBS) if trs_gbs else None, "traffic": None,
+                     "avg_launch_ms": trs_ms, "launches": trs[0]},
+        "kernels": {"spmv": {"GB/s": spm_gbs, "avg_ms": spm_ms, "launches": spm[0]},
+                    "orth": {"GB/s": orth_gbs, "avg_ms": orth_ms, "launches": orth[0]}},
+        "phases_s": {k: last[k] for k in ("t_build_s", "t_rcm_s", "t_factor_s", "t_solve_s", "t_post_s")},
+        "solve_phase_solves_per_s": batch / solve_s,
+        "gmres": last["gmres"],
+        "ilu": last["ilu"],
+        "order": last["order"],
+        "max_relres": float(max(lres["relres"])),
+    }
+    if not args.no_cpu_baseline:
+        log("timing the oracle on the host")
+        out["cpu_baseline"] = cpu_baseline(params, opts, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

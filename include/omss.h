@@ -271,6 +271,23 @@ om_status om_param_gradient(const om_csr* A, const void* x, const void* lambda, 
 void om_csr_free(om_csr* A);
 void om_ilu_free(om_ilu* M);
 
+/* ---- kernel timing (diagnostics) -----------------------------------------
+ * When enabled, every launch of an instrumented kernel class records a pair of
+ * HIP events on the stream it is launched on, together with the algorithmic
+ * bytes that launch moves.  Classes:
+ *   "trsv"  one triangular solve over all batch items (two per ilu_apply);
+ *           bytes = sum over items of nnz_T * (s + 4) + 2 n s (+ n s for the
+ *           pivot scaling of U-type solves), s = 16 (complex128) or 8;
+ *   "spmv"  one SpMV or FP64 residual over all batch items;
+ *           bytes = sum over items of nnz (s + 4) + 4 (n + 1) + 2 n s;
+ *   "orth"  one Gram-Schmidt pass (dots or update) of an Arnoldi step.
+ * om_profile_query waits for the recorded events of the class and returns the
+ * number of launches, their summed duration (ms) and summed bytes.  The
+ * counters are process-wide; om_profile_reset clears them. */
+void om_profile_enable(int32_t on);
+void om_profile_reset(void);
+om_status om_profile_query(const char* kernel_class, int64_t* launches, double* total_ms, double* bytes);
+
 /* ---- host-only entry points (no device; used for CPU checks of the host
  * algorithms) ------------------------------------------------------------- */
 

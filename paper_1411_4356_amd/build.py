@@ -38,7 +38,7 @@ def _compile(src: str, verbose: bool) -> str:
     if src.endswith(".hip"):
         cmd = [_hipcc(), "-x", "hip", "-c", src, "-o", obj] + COMMON + HIP_ONLY
     else:
-        cmd = [_hipcc(), "-c", src, "-o", obj] + COMMON + HOST_ONLY
+        cmd = [_hipcc(), "-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I", "/opt/rocm/include", "-c", src, "-o", obj] + COMMON + HOST_ONLY
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -124,8 +124,8 @@ struct HostFactor;
 // dinv (optional): per-row factor applied to the right-hand side (the
 // inverse pivots of U, whose rows are stored scaled to unit diagonal).
 struct TriSched {
-    int64_t n = 0, nblk = 0, nslots = 0;
-    bool rev = false;
+    int64_t n = 0, nblk = 0, nslots = 0, nnz = 0;
+    bool rev = false, has_dinv = false;
     int64_t depth = 0;
     DevBuf<int64_t> off;
     DevBuf<int32_t> col;

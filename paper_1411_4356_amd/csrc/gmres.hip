@@ -25,6 +25,7 @@
 #include "cplx.hpp"
 #include "gmres.hpp"
 #include "kernels.hpp"
+#include "profile.hpp"
 
 namespace omss {
 
@@ -416,7 +417,7 @@ om_status gmres_core(const om_csr* A, const om_ilu* M, int adjoint, const VT* b,
     std::vector<int32_t> act(B);
     while (true) {
         // true residual
-        OM_TRY(residual<VT>(A, adjoint, b, x, r, W.np.p, nullptr, nullptr, s));
+        OM_TRY(residual<VT>(A, adjoint, b, x, r, W.np.p, nullptr, nullptr, s, item_mask ? item_mask->data() : nullptr));
         hipLaunchKernelGGL(sum_partials_kernel, dim3(B), dim3(BT), 0, s, W.np.p, W.nres, W.beta2.p);
         OM_HIP(hipMemcpyAsync(W.h_d, W.beta2.p, B * sizeof(double), hipMemcpyDeviceToHost, s));
         OM_HIP(hipStreamSynchronize(s));
@@ -441,19 +442,27 @@ om_status gmres_core(const om_csr* A, const om_ilu* M, int adjoint, const VT* b,
         hipLaunchKernelGGL(scale_kernel<VT>, vgrid, dim3(BT), 0, s, r, V, n, W.beta2.p, W.act_cyc.p);
         OM_HIP(hipGetLastError());
         const unsigned ig = blocks_for(B, 64);
+        std::vector<int32_t> arn(act);
+        int narn = nact;
         for (int j = 0; j < m; ++j) {
             VT* vj = V + (int64_t)j * kstride;
             const VT* zin = vj;
             if (M) {
-                OM_TRY(ilu_apply_dev(M, adjoint, dtype, vj, z, W.act_arn.p, s));
+                OM_TRY(ilu_apply_dev(M, adjoint, dtype, vj, z, W.act_arn.p, s, arn.data()));
                 zin = z;
             }
-            OM_TRY(spmv<VT>(A, adjoint, zin, w, W.act_arn.p, s));
+            OM_TRY(spmv<VT>(A, adjoint, zin, w, W.act_arn.p, s, arn.data()));
             dim3 tgrid(W.ntile, B);
+            const double vb = (double)narn * (double)n * sizeof(VT);
             for (int pass = 0; pass < 2; ++pass) {
-                hipLaunchKernelGGL(mdot_kernel<VT>, tgrid, dim3(BT), 0, s, V, kstride, n, j + 1, w, W.part.p, W.act_arn.p);
-                hipLaunchKernelGGL(mdot_finalize_kernel, dim3(B), dim3(KMAX), 0, s, W.part.p, W.ntile, j + 1, W.h.p,
-                                   W.hsum.p, pass, W.act_arn.p);
+                {
+                    ProfScope prof("orth", s, vb * (j + 2));
+                    hipLaunchKernelGGL(mdot_kernel<VT>, tgrid, dim3(BT), 0, s, V, kstride, n, j + 1, w, W.part.p,
+                                       W.act_arn.p);
+                    hipLaunchKernelGGL(mdot_finalize_kernel, dim3(B), dim3(KMAX), 0, s, W.part.p, W.ntile, j + 1, W.h.p,
+                                       W.hsum.p, pass, W.act_arn.p);
+                }
+                ProfScope prof("orth", s, vb * (j + 3));
                 hipLaunchKernelGGL(update_kernel<VT>, vgrid, dim3(BT), 0, s, V, kstride, n, j + 1, W.h.p, w,
                                    pass == 1 ? W.np.p : nullptr, W.act_arn.p);
             }
@@ -467,7 +476,10 @@ om_status gmres_core(const om_csr* A, const om_ilu* M, int adjoint, const VT* b,
             OM_HIP(hipMemcpyAsync(W.h_est, W.est.p, B * sizeof(double), hipMemcpyDeviceToHost, s));
             OM_HIP(hipStreamSynchronize(s));
             bool any = false;
+            narn = 0;
             for (int i = 0; i < B; ++i) {
+                arn[i] = act[i] ? W.h_act[i] : 0;
+                narn += arn[i] != 0;
                 if (!act[i]) continue;
                 res.est[i] = W.h_est[i];
                 if (!std::isfinite(W.h_est[i])) { set_error("GMRES breakdown: non-finite residual estimate (item %d)", i); return OM_EBREAKDOWN; }
@@ -489,7 +501,7 @@ om_status gmres_core(const om_csr* A, const om_ilu* M, int adjoint, const VT* b,
         hipLaunchKernelGGL(combine_kernel<VT>, vgrid, dim3(BT), 0, s, V, kstride, n, W.y.p, W.steps.p, w, W.act_cyc.p);
         const VT* upd = w;
         if (M) {
-            OM_TRY(ilu_apply_dev(M, adjoint, dtype, w, z, W.act_cyc.p, s));
+            OM_TRY(ilu_apply_dev(M, adjoint, dtype, w, z, W.act_cyc.p, s, act.data()));
             upd = z;
         }
         hipLaunchKernelGGL((axpy_kernel<VT, VT>), vgrid, dim3(BT), 0, s, x, upd, n, (const double*)nullptr, W.act_cyc.p);

@@ -70,7 +70,7 @@ om_status ilu_factor_impl(const om_csr* Ain, double drop_tol, double fill_factor
             std::unique_ptr<HostFactor> F(new HostFactor);
             std::string err;
             ilut_factor_host(n, A->h_row_ptr.data(), A->h_col.data(), vals.data() + (size_t)b * nnz * 2, drop_tol,
-                             fill_factor, F.get(), &err);
+                             fill_factor, 0.0, F.get(), &err);
             nl[b] = (int64_t)F->l_col.size();
             nu[b] = (int64_t)F->u_col.size();
             rep[b] = F->repaired;
@@ -139,7 +139,7 @@ om_status host_ilut_impl(int64_t n, const int64_t* row_ptr, const int32_t* col, 
     M->host.resize(1);
     M->host[0].reset(new HostFactor);
     std::string err;
-    ilut_factor_host(n, row_ptr, col, val, drop_tol, fill_factor, M->host[0].get(), &err);
+    ilut_factor_host(n, row_ptr, col, val, drop_tol, fill_factor, 0.0, M->host[0].get(), &err);
     const HostFactor& F = *M->host[0];
     om_ilu_stats S{};
     S.nnz_L = (int64_t)F.l_col.size();

@@ -11,12 +11,14 @@ struct HostFactor {
     std::vector<int64_t> l_ptr, u_ptr;
     std::vector<int32_t> l_col, u_col;
     std::vector<double> l_val, u_val;   // interleaved re, im
+    std::vector<int32_t> perm;          // column permutation Q: perm[position] = column
     int64_t repaired = 0;
+    int64_t pivots = 0;                 // column exchanges made by threshold pivoting
 };
 
 // Factor the n x n CSR matrix (values interleaved re,im; columns sorted per
-// row).  Returns 0 on success.
+// row), A Q ~ L U.  permtol = 0 disables pivoting.  Returns 0 on success.
 int ilut_factor_host(int64_t n, const int64_t* row_ptr, const int32_t* col, const double* val,
-                     double drop_tol, double fill_factor, HostFactor* out, std::string* err);
+                     double drop_tol, double fill_factor, double permtol, HostFactor* out, std::string* err);
 
 }  // namespace omss

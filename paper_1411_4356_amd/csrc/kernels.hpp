@@ -18,15 +18,18 @@ om_status ensure_transpose(om_csr* A, hipStream_t s);
 
 // spmv.hip: y = A x or A^H x; VT = double2 or float2
 template <typename VT>
-om_status spmv(const om_csr* A, int adjoint, const VT* x, VT* y, const int32_t* active, hipStream_t s);
+om_status spmv(const om_csr* A, int adjoint, const VT* x, VT* y, const int32_t* active, hipStream_t s,
+               const int32_t* act_host = nullptr);
 // r = b - A x and per-item partial |r|^2 into norm2 (*nparts per item); with
 // b == nullptr only *nparts is returned.
 template <typename VT>
 om_status residual(const om_csr* A, int adjoint, const VT* b, const VT* x, VT* r, double* norm2, int* nparts,
-                   const int32_t* active, hipStream_t s);
+                   const int32_t* active, hipStream_t s, const int32_t* act_host = nullptr);
+double spmv_bytes(const om_csr* A, size_t s, const int32_t* act_host);
 
 // trsv.hip
+// act_host (nullable): host copy of the active mask, used for byte accounting
 om_status ilu_apply_dev(const om_ilu* M, int adjoint, int dtype, const void* x, void* y, const int32_t* active,
-                        hipStream_t s);
+                        hipStream_t s, const int32_t* act_host = nullptr);
 
 }  // namespace omss

@@ -1,0 +1,25 @@
+// Kernel timing with HIP events recorded on the launch stream (diagnostics).
+#pragma once
+#include "common.hpp"
+
+namespace omss {
+
+bool profile_enabled();
+
+// Records a start event on construction and a stop event on destruction for
+// kernel class `cls`, accounting `bytes` algorithmic bytes to the launch.
+class ProfScope {
+public:
+    ProfScope(const char* cls, hipStream_t s, double bytes);
+    ~ProfScope();
+    ProfScope(const ProfScope&) = delete;
+    ProfScope& operator=(const ProfScope&) = delete;
+
+private:
+    const char* cls_;
+    hipStream_t s_;
+    double bytes_;
+    hipEvent_t a_ = nullptr, b_ = nullptr;
+};
+
+}  // namespace omss

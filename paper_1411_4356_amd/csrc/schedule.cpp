@@ -48,6 +48,7 @@ void build_host_tri(const SolveCSR& T, HostTri& H) {
     H.n = n;
     H.nblk = (n + BLK - 1) / BLK;
     H.depth = level_depth(n, T.ptr, T.col);
+    H.nnz = T.ptr[n];
     H.off.assign(H.nblk + 1, 0);
     for (int64_t g = 0; g < H.nblk; ++g) {
         const int64_t r0 = g * BLK;
@@ -215,6 +216,8 @@ om_status upload_tri(const HostTri& H, bool c64, TriSched& S) {
     S.nslots = H.off.empty() ? 0 : H.off.back();
     S.rev = H.rev;
     S.depth = H.depth;
+    S.nnz = H.nnz;
+    S.has_dinv = !H.dinv.empty();
     OM_TRY(up(S.off, H.off.data(), H.off.size()));
     OM_TRY(up(S.col, H.col.data(), H.col.size()));
     OM_TRY(up(S.val, H.val.data(), H.val.size() / 2));

@@ -20,7 +20,7 @@ struct SolveCSR {
 };
 
 struct HostTri {
-    int64_t n = 0, nblk = 0, depth = 0;
+    int64_t n = 0, nblk = 0, depth = 0, nnz = 0;
     bool rev = false;
     std::vector<int64_t> off;
     std::vector<int32_t> col;

@@ -9,6 +9,7 @@
 #include "common.hpp"
 #include "cplx.hpp"
 #include "kernels.hpp"
+#include "profile.hpp"
 
 namespace omss {
 
@@ -49,8 +50,18 @@ __global__ __launch_bounds__(256) void spmv_kernel(const int32_t* __restrict__ r
     }
 }
 
+double spmv_bytes(const om_csr* A, size_t s, const int32_t* act_host) {
+    int na = A->batch;
+    if (act_host) {
+        na = 0;
+        for (int i = 0; i < A->batch; ++i) na += act_host[i] != 0;
+    }
+    return na * ((double)A->nnz * (double)(s + 4) + 4.0 * (double)(A->n + 1) + 2.0 * (double)A->n * (double)s);
+}
+
 template <typename VT>
-om_status spmv(const om_csr* A, int adjoint, const VT* x, VT* y, const int32_t* active, hipStream_t s) {
+om_status spmv(const om_csr* A, int adjoint, const VT* x, VT* y, const int32_t* active, hipStream_t s,
+               const int32_t* act_host) {
     constexpr int G = 8;
     const int TPB = 256;
     const int32_t* rp = adjoint ? A->t_row_ptr.p : A->row_ptr.p;
@@ -60,12 +71,15 @@ om_status spmv(const om_csr* A, int adjoint, const VT* x, VT* y, const int32_t* 
     else v = adjoint ? (const void*)A->t_val32.p : (const void*)A->val32.p;
     if (!rp || !cl || !v) { set_error("spmv: matrix storage for this product was not built"); return OM_EINVAL; }
     dim3 grid(blocks_for(A->n * G, TPB), A->batch);
+    ProfScope prof("spmv", s, profile_enabled() ? spmv_bytes(A, sizeof(VT), act_host) : 0.0);
     hipLaunchKernelGGL((spmv_kernel<VT, G>), grid, dim3(TPB), 0, s, rp, cl, (const VT*)v, A->nnz, x, y, A->n, active);
     OM_HIP(hipGetLastError());
     return OM_OK;
 }
-template om_status spmv<double2>(const om_csr*, int, const double2*, double2*, const int32_t*, hipStream_t);
-template om_status spmv<float2>(const om_csr*, int, const float2*, float2*, const int32_t*, hipStream_t);
+template om_status spmv<double2>(const om_csr*, int, const double2*, double2*, const int32_t*, hipStream_t,
+                                 const int32_t*);
+template om_status spmv<float2>(const om_csr*, int, const float2*, float2*, const int32_t*, hipStream_t,
+                                const int32_t*);
 
 // r = b - A x with the squared norm of r accumulated per block:
 // norm2[b * gridDim.x + blockIdx.x] (always in double precision).
@@ -116,7 +130,7 @@ __global__ __launch_bounds__(256) void residual_kernel(const int32_t* __restrict
 
 template <typename VT>
 om_status residual(const om_csr* A, int adjoint, const VT* b, const VT* x, VT* r, double* norm2, int* nparts,
-                   const int32_t* active, hipStream_t s) {
+                   const int32_t* active, hipStream_t s, const int32_t* act_host) {
     constexpr int G = 8;
     const int TPB = 256;
     const int32_t* rp = adjoint ? A->t_row_ptr.p : A->row_ptr.p;
@@ -128,14 +142,15 @@ om_status residual(const om_csr* A, int adjoint, const VT* b, const VT* x, VT* r
     dim3 grid(blocks_for(A->n * G, TPB), A->batch);
     if (nparts) *nparts = (int)grid.x;
     if (!b) return OM_OK;
+    ProfScope prof("spmv", s, profile_enabled() ? spmv_bytes(A, sizeof(VT), act_host) + A->batch * (double)A->n * sizeof(VT) : 0.0);
     hipLaunchKernelGGL((residual_kernel<VT, G>), grid, dim3(TPB), 0, s, rp, cl, (const VT*)v, A->nnz, b, x, r, norm2,
                        A->n, active);
     OM_HIP(hipGetLastError());
     return OM_OK;
 }
 template om_status residual<double2>(const om_csr*, int, const double2*, const double2*, double2*, double*, int*,
-                                     const int32_t*, hipStream_t);
+                                     const int32_t*, hipStream_t, const int32_t*);
 template om_status residual<float2>(const om_csr*, int, const float2*, const float2*, float2*, double*, int*,
-                                    const int32_t*, hipStream_t);
+                                    const int32_t*, hipStream_t, const int32_t*);
 
 }  // namespace omss

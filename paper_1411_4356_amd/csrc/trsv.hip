@@ -13,6 +13,7 @@
 // One workgroup owns one batch item, so batch items are solved concurrently.
 #include "common.hpp"
 #include "cplx.hpp"
+#include "profile.hpp"
 
 namespace omss {
 
@@ -85,29 +86,39 @@ __global__ __launch_bounds__(64 * TRSV_WAVES) void trsv_block_kernel(const TriVi
     }
 }
 
+// Algorithmic bytes of one triangular solve over the active items: values and
+// column indices of the factor, right-hand side read, solution written, and
+// the pivot scaling where present.
+static double trsv_bytes(const om_ilu* M, int kind, size_t s, const int32_t* act_host) {
+    double b = 0.0;
+    for (int i = 0; i < M->batch; ++i) {
+        if (act_host && !act_host[i]) continue;
+        const TriSched& S = M->sched[(size_t)i * 4 + kind];
+        b += (double)S.nnz * (double)(s + 4) + 2.0 * (double)S.n * (double)s + (S.has_dinv ? (double)S.n * s : 0.0);
+    }
+    return b;
+}
+
 template <typename VT>
-om_status launch_trsv(const TriView<VT>* views, int kind, int batch, const VT* rhs, VT* out, int64_t n,
-                      const int32_t* active, hipStream_t s) {
-    hipLaunchKernelGGL(trsv_block_kernel<VT>, dim3(batch), dim3(64 * TRSV_WAVES), 0, s, views, kind, rhs, out, n, active);
+om_status launch_trsv(const om_ilu* M, const TriView<VT>* views, int kind, const VT* rhs, VT* out,
+                      const int32_t* active, const int32_t* act_host, hipStream_t s) {
+    ProfScope prof("trsv", s, profile_enabled() ? trsv_bytes(M, kind, sizeof(VT), act_host) : 0.0);
+    hipLaunchKernelGGL(trsv_block_kernel<VT>, dim3(M->batch), dim3(64 * TRSV_WAVES), 0, s, views, kind, rhs, out, M->n,
+                       active);
     OM_HIP(hipGetLastError());
     return OM_OK;
 }
 
-template om_status launch_trsv<double2>(const TriView<double2>*, int, int, const double2*, double2*, int64_t,
-                                        const int32_t*, hipStream_t);
-template om_status launch_trsv<float2>(const TriView<float2>*, int, int, const float2*, float2*, int64_t,
-                                       const int32_t*, hipStream_t);
-
 // y = (L U)^{-1} x or (L U)^{-H} x for every active batch item; x, y may alias.
 om_status ilu_apply_dev(const om_ilu* M, int adjoint, int dtype, const void* x, void* y, const int32_t* active,
-                        hipStream_t s) {
+                        hipStream_t s, const int32_t* act_host) {
     const int k0 = adjoint ? 2 : 0, k1 = adjoint ? 3 : 1;
     if (dtype == OM_C128) {
-        OM_TRY(launch_trsv<double2>(M->views64.p, k0, M->batch, (const double2*)x, (double2*)y, M->n, active, s));
-        OM_TRY(launch_trsv<double2>(M->views64.p, k1, M->batch, (const double2*)y, (double2*)y, M->n, active, s));
+        OM_TRY(launch_trsv<double2>(M, M->views64.p, k0, (const double2*)x, (double2*)y, active, act_host, s));
+        OM_TRY(launch_trsv<double2>(M, M->views64.p, k1, (const double2*)y, (double2*)y, active, act_host, s));
     } else {
-        OM_TRY(launch_trsv<float2>(M->views32.p, k0, M->batch, (const float2*)x, (float2*)y, M->n, active, s));
-        OM_TRY(launch_trsv<float2>(M->views32.p, k1, M->batch, (const float2*)y, (float2*)y, M->n, active, s));
+        OM_TRY(launch_trsv<float2>(M, M->views32.p, k0, (const float2*)x, (float2*)y, active, act_host, s));
+        OM_TRY(launch_trsv<float2>(M, M->views32.p, k1, (const float2*)y, (float2*)y, active, act_host, s));
     }
     return OM_OK;
 }
