@@ -230,7 +230,7 @@ om_status ilu_apply(const om_ilu* M, int32_t adjoint, int32_t dtype, const void*
         if (dtype == OM_C64 && !(M->flags & OM_ILU_C64)) { set_error("factors were built without OM_ILU_C64"); return OM_EINVAL; }
         if (dtype != OM_C64 && dtype != OM_C128) { set_error("bad dtype"); return OM_EINVAL; }
         OM_TRY(ilu_apply_dev(M, adjoint, dtype, x, y, nullptr, as_stream(stream)));
-        return OM_OK;
+        return trsv_check(M, as_stream(stream));
     });
 }
 

@@ -115,38 +115,47 @@ namespace omss {
 struct HostFactor;
 
 // One unit-lower triangular solve in "solve coordinates" (an upper factor is
-// stored row- and column-reversed so that it is lower triangular too).
-// Rows are grouped in blocks of 64 (one wavefront).  For every block:
-//   - the entries left of the block are stored slot-major (ELL): slot s of
-//     row r at [(off[g] + s) * 64 + r], padded with column 0 / value 0;
-//   - the strictly-lower 64x64 diagonal block is stored packed by column:
-//     column c holds rows c+1..63 at [g * 2016 + c*63 - c*(c-1)/2 + (r-c-1)].
-// dinv (optional): per-row factor applied to the right-hand side (the
-// inverse pivots of U, whose rows are stored scaled to unit diagonal).
+// stored row- and column-reversed so that it is lower triangular too); see
+// schedule.cpp for the layout.  dinv (optional): per-row factor applied to the
+// right-hand side (the inverse pivots of U, whose rows are stored scaled).
 struct TriSched {
-    int64_t n = 0, nblk = 0, nslots = 0, nnz = 0;
+    int64_t n = 0, nblk = 0, nslots_far = 0, nslots_near = 0, nnz = 0;
     bool rev = false, has_dinv = false;
     int64_t depth = 0;
-    DevBuf<int64_t> off;
-    DevBuf<int32_t> col;
-    DevBuf<double2> val;
-    DevBuf<float2> val32;
-    DevBuf<double2> dg;
-    DevBuf<float2> dg32;
-    DevBuf<double2> dinv;
-    DevBuf<float2> dinv32;
+    DevBuf<int64_t> far_off, mid_off, near_off;
+    DevBuf<int32_t> far_col, mid_col, near_col, far_need;
+    DevBuf<double2> far_val, mid_val, near_val, dg, dinv;
+    DevBuf<float2> far_val32, mid_val32, near_val32, dg32, dinv32;
 };
 
 // POD view of a TriSched for kernels.
 template <typename VT>
 struct TriView {
-    const int64_t* off;
-    const int32_t* col;
-    const VT* val;
+    const int64_t* far_off;
+    const int64_t* mid_off;
+    const int64_t* near_off;
+    const int32_t* far_col;
+    const int32_t* mid_col;
+    const int32_t* near_col;
+    const int32_t* far_need;
+    const VT* far_val;
+    const VT* mid_val;
+    const VT* near_val;
     const VT* dg;
     const VT* dinv;   // may be null
     int64_t n, nblk;
     int32_t rev;
+};
+
+// Device scratch shared by the cooperative triangular solves of one factor
+// set: per item the far partial sums and ready flags of every block, a
+// progress counter, and one abort flag.
+struct TrsvScratch {
+    DevBuf<double2> far_buf;    // batch * nblk * 64 (complex64 kernels use half of it)
+    DevBuf<int32_t> fdone;      // batch * nblk, epoch tags
+    DevBuf<int64_t> progress;   // batch, (epoch << 32) | blocks done
+    DevBuf<int32_t> abort_flag; // 1 word
+    uint32_t epoch = 0;
 };
 
 }  // namespace omss
@@ -161,5 +170,6 @@ struct om_ilu {
     std::vector<omss::TriSched> sched;                     // batch * 4
     omss::DevBuf<omss::TriView<double2>> views64;          // batch * 4
     omss::DevBuf<omss::TriView<float2>> views32;           // batch * 4
+    omss::TrsvScratch scratch;
     om_ilu_stats stats{};
 };

@@ -475,6 +475,7 @@ om_status gmres_core(const om_csr* A, const om_ilu* M, int adjoint, const VT* b,
             OM_HIP(hipMemcpyAsync(W.h_act, W.act_arn.p, B * sizeof(int32_t), hipMemcpyDeviceToHost, s));
             OM_HIP(hipMemcpyAsync(W.h_est, W.est.p, B * sizeof(double), hipMemcpyDeviceToHost, s));
             OM_HIP(hipStreamSynchronize(s));
+            if (M) OM_TRY(trsv_check(M, s));
             bool any = false;
             narn = 0;
             for (int i = 0; i < B; ++i) {
@@ -508,6 +509,7 @@ om_status gmres_core(const om_csr* A, const om_ilu* M, int adjoint, const VT* b,
         OM_HIP(hipGetLastError());
         OM_HIP(hipMemcpyAsync(W.h_steps, W.steps.p, B * sizeof(int32_t), hipMemcpyDeviceToHost, s));
         OM_HIP(hipStreamSynchronize(s));
+        if (M) OM_TRY(trsv_check(M, s));
         for (int i = 0; i < B; ++i)
             if (act[i]) {
                 res.iters[i] += W.h_steps[i];

@@ -4,6 +4,7 @@
 #include <chrono>
 #include <cmath>
 #include <mutex>
+#include <string>
 #include <thread>
 
 #include "common.hpp"
@@ -23,14 +24,27 @@ static om_status finish_views(om_ilu* M, hipStream_t s) {
         for (int k = 0; k < 4; ++k) {
             const TriSched& S = M->sched[(size_t)b * 4 + k];
             TriView<double2>& a = v64[(size_t)b * 4 + k];
-            a.off = S.off.p; a.col = S.col.p; a.val = S.val.p; a.dg = S.dg.p; a.dinv = S.dinv.p;
-            a.n = S.n; a.nblk = S.nblk; a.rev = S.rev;
+            a.far_off = S.far_off.p; a.mid_off = S.mid_off.p; a.near_off = S.near_off.p; a.far_col = S.far_col.p;
+            a.mid_col = S.mid_col.p; a.near_col = S.near_col.p; a.far_need = S.far_need.p; a.far_val = S.far_val.p;
+            a.mid_val = S.mid_val.p; a.near_val = S.near_val.p; a.dg = S.dg.p;
+            a.dinv = S.dinv.p; a.n = S.n; a.nblk = S.nblk; a.rev = S.rev;
             TriView<float2>& c = v32[(size_t)b * 4 + k];
-            c.off = S.off.p; c.col = S.col.p; c.val = S.val32.p; c.dg = S.dg32.p; c.dinv = S.dinv32.p;
-            c.n = S.n; c.nblk = S.nblk; c.rev = S.rev;
+            c.far_off = S.far_off.p; c.mid_off = S.mid_off.p; c.near_off = S.near_off.p; c.far_col = S.far_col.p;
+            c.mid_col = S.mid_col.p; c.near_col = S.near_col.p; c.far_need = S.far_need.p; c.far_val = S.far_val32.p;
+            c.mid_val = S.mid_val32.p; c.near_val = S.near_val32.p; c.dg = S.dg32.p;
+            c.dinv = S.dinv32.p; c.n = S.n; c.nblk = S.nblk; c.rev = S.rev;
         }
     OM_TRY(M->views64.upload(v64.data(), v64.size(), s));
     OM_TRY(M->views32.upload(v32.data(), v32.size(), s));
+    const int64_t nblk = (M->n + 63) / 64;
+    OM_TRY(M->scratch.far_buf.alloc((size_t)B * nblk * 64));
+    OM_TRY(M->scratch.fdone.alloc((size_t)B * nblk));
+    OM_TRY(M->scratch.progress.alloc(B));
+    OM_TRY(M->scratch.abort_flag.alloc(1));
+    OM_HIP(hipMemsetAsync(M->scratch.fdone.p, 0, M->scratch.fdone.bytes(), s));
+    OM_HIP(hipMemsetAsync(M->scratch.progress.p, 0, M->scratch.progress.bytes(), s));
+    OM_HIP(hipMemsetAsync(M->scratch.abort_flag.p, 0, M->scratch.abort_flag.bytes(), s));
+    M->scratch.epoch = 0;
     OM_HIP(hipStreamSynchronize(s));
     return OM_OK;
 }
@@ -69,8 +83,12 @@ om_status ilu_factor_impl(const om_csr* Ain, double drop_tol, double fill_factor
         for (int b = t; b < B; b += T) {
             std::unique_ptr<HostFactor> F(new HostFactor);
             std::string err;
-            ilut_factor_host(n, A->h_row_ptr.data(), A->h_col.data(), vals.data() + (size_t)b * nnz * 2, drop_tol,
-                             fill_factor, 0.0, F.get(), &err);
+            if (ilut_factor_host(n, A->h_row_ptr.data(), A->h_col.data(), vals.data() + (size_t)b * nnz * 2, drop_tol,
+                                 fill_factor, 0.0, F.get(), &err) != 0) {
+                status[b] = OM_EBREAKDOWN;
+                errs[b] = "batch item " + std::to_string(b) + ": " + err;
+                continue;
+            }
             nl[b] = (int64_t)F->l_col.size();
             nu[b] = (int64_t)F->u_col.size();
             rep[b] = F->repaired;
@@ -139,7 +157,10 @@ om_status host_ilut_impl(int64_t n, const int64_t* row_ptr, const int32_t* col, 
     M->host.resize(1);
     M->host[0].reset(new HostFactor);
     std::string err;
-    ilut_factor_host(n, row_ptr, col, val, drop_tol, fill_factor, 0.0, M->host[0].get(), &err);
+    if (ilut_factor_host(n, row_ptr, col, val, drop_tol, fill_factor, 0.0, M->host[0].get(), &err) != 0) {
+        set_error("%s", err.c_str());
+        return OM_EBREAKDOWN;
+    }
     const HostFactor& F = *M->host[0];
     om_ilu_stats S{};
     S.nnz_L = (int64_t)F.l_col.size();

@@ -11,7 +11,9 @@
 // lfil_i = floor((p * nnz(a_i) - 1) / 2) entries are kept in each triangle,
 // largest modulus first, ties to the lower column.  A pivot below
 // 1e-14 * ||a_i||_inf is raised to that floor (same phase) and counted.
-// Magnitudes are compared as squared moduli.
+// Magnitudes are compared as squared moduli.  A non-finite pivot or U entry
+// stops the factorisation (breakdown: the incomplete factors have grown
+// without bound, which happens when too much fill is dropped).
 //
 // Columns are tracked by their original index while the factorisation runs
 // (pivoting renumbers positions >= i only, so positions < i are final); the
@@ -23,6 +25,7 @@
 #include <cmath>
 #include <cstring>
 #include <queue>
+#include <string>
 #include <vector>
 
 namespace omss {
@@ -169,6 +172,16 @@ int ilut_factor_host(int64_t n, const int64_t* row_ptr, const int32_t* col, cons
         }
         std::sort(lower.begin(), lower.end(), [](const Entry& a, const Entry& b) { return a.pos < b.pos; });
 
+        if (!std::isfinite(dgr) || !std::isfinite(dgi)) {
+            if (err) *err = "ILUT breakdown: non-finite pivot in row " + std::to_string(i) +
+                            " (the incomplete factorisation is unstable for this drop tolerance and fill)";
+            return 1;
+        }
+        for (const Entry& e : upper)
+            if (!std::isfinite(e.re) || !std::isfinite(e.im)) {
+                if (err) *err = "ILUT breakdown: non-finite entry in row " + std::to_string(i);
+                return 1;
+            }
         const double fl = floor_rel * rowinf;
         const double dmag = std::sqrt(dgr * dgr + dgi * dgi);
         if (dmag < fl || dmag == 0.0) {
@@ -211,7 +224,6 @@ int ilut_factor_host(int64_t n, const int64_t* row_ptr, const int32_t* col, cons
         }
     }
     F.perm = perm;
-    (void)err;
     return 0;
 }
 

@@ -31,5 +31,6 @@ double spmv_bytes(const om_csr* A, size_t s, const int32_t* act_host);
 // act_host (nullable): host copy of the active mask, used for byte accounting
 om_status ilu_apply_dev(const om_ilu* M, int adjoint, int dtype, const void* x, void* y, const int32_t* active,
                         hipStream_t s, const int32_t* act_host = nullptr);
+om_status trsv_check(const om_ilu* M, hipStream_t s);
 
 }  // namespace omss

@@ -9,10 +9,12 @@
 // right-hand side instead.
 //
 // Rows are grouped in blocks of 64 (one wavefront).  The entries of a block
-// that lie left of the block are stored slot-major (ELL): slot s of row r at
-// [(off[g] + s) * 64 + r], columns increasing with s, short rows padded with
-// column 0 and value 0.  The strictly-lower part of the 64x64 diagonal block is
-// stored dense and packed by column.
+// that lie left of it are stored slot-major (ELL) in three lists by the block
+// of their column: "near" (block g-1), "mid" (block g-2) and "far" (older);
+// slot s of row r of block g is at [(off[g] + s) * 64 + r], columns
+// increasing with s, short rows padded with value 0.  For every far slot,
+// need[slot] is the newest column block it reads.  The strictly-lower part of
+// the 64x64 diagonal block is stored dense and packed by column.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -49,41 +51,67 @@ void build_host_tri(const SolveCSR& T, HostTri& H) {
     H.nblk = (n + BLK - 1) / BLK;
     H.depth = level_depth(n, T.ptr, T.col);
     H.nnz = T.ptr[n];
-    H.off.assign(H.nblk + 1, 0);
+    H.far_off.assign(H.nblk + 1, 0);
+    H.mid_off.assign(H.nblk + 1, 0);
+    H.near_off.assign(H.nblk + 1, 0);
+    // class of a column c for block g: 0 far, 1 mid, 2 near, 3 diagonal block
+    auto cls = [](int64_t c, int64_t g) -> int {
+        const int64_t cb = c / BLK;
+        if (cb == g) return 3;
+        if (cb == g - 1) return 2;
+        if (cb == g - 2) return 1;
+        return 0;
+    };
+    std::vector<int64_t>* offs[3] = {&H.far_off, &H.mid_off, &H.near_off};
     for (int64_t g = 0; g < H.nblk; ++g) {
         const int64_t r0 = g * BLK;
-        int64_t ns = 0;
+        int64_t mx[3] = {0, 0, 0};
         for (int r = 0; r < BLK && r0 + r < n; ++r) {
             const int64_t i = r0 + r;
-            int64_t c = 0;
-            for (int64_t t = T.ptr[i]; t < T.ptr[i + 1] && T.col[t] < r0; ++t) ++c;
-            ns = std::max(ns, c);
+            int64_t cnt[4] = {0, 0, 0, 0};
+            for (int64_t t = T.ptr[i]; t < T.ptr[i + 1]; ++t) cnt[cls(T.col[t], g)]++;
+            for (int k = 0; k < 3; ++k) mx[k] = std::max(mx[k], cnt[k]);
         }
-        H.off[g + 1] = H.off[g] + ns;
+        for (int k = 0; k < 3; ++k) (*offs[k])[g + 1] = (*offs[k])[g] + mx[k];
     }
-    const int64_t nslots = H.off[H.nblk];
-    H.col.assign((size_t)nslots * BLK, 0);
-    H.val.assign((size_t)nslots * BLK * 2, 0.0);
+    const int64_t nsf = H.far_off[H.nblk], nsm = H.mid_off[H.nblk], nsn = H.near_off[H.nblk];
+    H.far_col.assign((size_t)nsf * BLK, 0);
+    H.far_val.assign((size_t)nsf * BLK * 2, 0.0);
+    H.far_need.assign((size_t)nsf, 0);
+    H.mid_col.assign((size_t)nsm * BLK, 0);
+    H.mid_val.assign((size_t)nsm * BLK * 2, 0.0);
+    H.near_col.assign((size_t)nsn * BLK, 0);
+    H.near_val.assign((size_t)nsn * BLK * 2, 0.0);
     H.dg.assign((size_t)H.nblk * TRI * 2, 0.0);
+    std::vector<int32_t>* cols[3] = {&H.far_col, &H.mid_col, &H.near_col};
+    std::vector<double>* vals[3] = {&H.far_val, &H.mid_val, &H.near_val};
     for (int64_t g = 0; g < H.nblk; ++g) {
         const int64_t r0 = g * BLK;
+        // padding: a column of the list's own block (value 0), so that no read
+        // reaches an unfinished block
+        for (int k = 1; k < 3; ++k) {
+            const int32_t pad = (int32_t)std::max<int64_t>(0, (g - 3 + k) * BLK);
+            for (int64_t s = (*offs[k])[g]; s < (*offs[k])[g + 1]; ++s)
+                for (int r = 0; r < BLK; ++r) (*cols[k])[s * BLK + r] = pad;
+        }
         for (int r = 0; r < BLK && r0 + r < n; ++r) {
             const int64_t i = r0 + r;
-            int64_t s = 0;
+            int64_t sl[3] = {0, 0, 0};
             for (int64_t t = T.ptr[i]; t < T.ptr[i + 1]; ++t) {
                 const int64_t c = T.col[t];
-                if (c < r0) {
-                    const int64_t at = (H.off[g] + s) * BLK + r;
-                    H.col[at] = (int32_t)c;
-                    H.val[2 * at] = T.val[2 * t];
-                    H.val[2 * at + 1] = T.val[2 * t + 1];
-                    ++s;
-                } else {
-                    const int cc = (int)(c - r0);
-                    const int64_t at = g * TRI + tri_index(cc, r);
+                const int k = cls(c, g);
+                if (k == 3) {
+                    const int64_t at = g * TRI + tri_index((int)(c - r0), r);
                     H.dg[2 * at] = T.val[2 * t];
                     H.dg[2 * at + 1] = T.val[2 * t + 1];
+                    continue;
                 }
+                const int64_t slot = (*offs[k])[g] + sl[k]++;
+                const int64_t at = slot * BLK + r;
+                (*cols[k])[at] = (int32_t)c;
+                (*vals[k])[2 * at] = T.val[2 * t];
+                (*vals[k])[2 * at + 1] = T.val[2 * t + 1];
+                if (k == 0) H.far_need[slot] = std::max<int32_t>(H.far_need[slot], (int32_t)(c / BLK));
             }
         }
     }
@@ -213,21 +241,33 @@ static void narrow(const std::vector<double>& in, std::vector<float>& out) {
 om_status upload_tri(const HostTri& H, bool c64, TriSched& S) {
     S.n = H.n;
     S.nblk = H.nblk;
-    S.nslots = H.off.empty() ? 0 : H.off.back();
     S.rev = H.rev;
     S.depth = H.depth;
     S.nnz = H.nnz;
     S.has_dinv = !H.dinv.empty();
-    OM_TRY(up(S.off, H.off.data(), H.off.size()));
-    OM_TRY(up(S.col, H.col.data(), H.col.size()));
-    OM_TRY(up(S.val, H.val.data(), H.val.size() / 2));
+    S.nslots_far = H.far_off.back();
+    S.nslots_near = H.near_off.back() + H.mid_off.back();
+    OM_TRY(up(S.far_off, H.far_off.data(), H.far_off.size()));
+    OM_TRY(up(S.mid_off, H.mid_off.data(), H.mid_off.size()));
+    OM_TRY(up(S.near_off, H.near_off.data(), H.near_off.size()));
+    OM_TRY(up(S.far_col, H.far_col.data(), H.far_col.size()));
+    OM_TRY(up(S.far_need, H.far_need.data(), H.far_need.size()));
+    OM_TRY(up(S.mid_col, H.mid_col.data(), H.mid_col.size()));
+    OM_TRY(up(S.near_col, H.near_col.data(), H.near_col.size()));
+    OM_TRY(up(S.far_val, H.far_val.data(), H.far_val.size() / 2));
+    OM_TRY(up(S.mid_val, H.mid_val.data(), H.mid_val.size() / 2));
+    OM_TRY(up(S.near_val, H.near_val.data(), H.near_val.size() / 2));
     OM_TRY(up(S.dg, H.dg.data(), H.dg.size() / 2));
     if (!H.dinv.empty()) OM_TRY(up(S.dinv, H.dinv.data(), H.dinv.size() / 2));
     else S.dinv.release();
     if (c64) {
         std::vector<float> f;
-        narrow(H.val, f);
-        OM_TRY(up(S.val32, f.data(), f.size() / 2));
+        narrow(H.far_val, f);
+        OM_TRY(up(S.far_val32, f.data(), f.size() / 2));
+        narrow(H.mid_val, f);
+        OM_TRY(up(S.mid_val32, f.data(), f.size() / 2));
+        narrow(H.near_val, f);
+        OM_TRY(up(S.near_val32, f.data(), f.size() / 2));
         narrow(H.dg, f);
         OM_TRY(up(S.dg32, f.data(), f.size() / 2));
         if (!H.dinv.empty()) {

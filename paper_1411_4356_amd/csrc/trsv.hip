@@ -1,19 +1,38 @@
 // Preconditioner application: blocked sparse triangular solves on the device.
 //
-// The factors of an RCM-ordered ILUT have a dependency depth close to n (each
-// row reads the one before it), so a level schedule has about one row per
-// level.  The solve therefore walks 64-row blocks in order.  For block g:
-//   1. every wave of the workgroup takes a share of the ELL slots of the
-//      block (entries left of the block, whose unknowns are final) and
-//      accumulates sum_j T[r, j] x[j] for its 64 rows (lane = row);
-//   2. wave 0 combines the partial sums with the right-hand side and solves
-//      the 64x64 unit-lower diagonal block by a column sweep: at step c the
-//      finished unknown of lane c is broadcast (readlane) and subtracted from
-//      the rows below it.
-// One workgroup owns one batch item, so batch items are solved concurrently.
+// The factors of an RCM-ordered ILUT are banded and their rows depend on the
+// rows just before them, so the solve walks 64-row blocks (one wavefront of
+// rows, lane = row) in order.  For block g the unknowns are
+//     x_g = T_gg^{-1} (dinv .* y_g - sum_{h < g} T_gh x_h),
+// T_gg unit lower triangular.  The entries left of the block are in three
+// slot-major lists by the block of their column (near = g-1, mid = g-2, far =
+// older); T_gg is swept column by column: at step c the finished unknown of
+// lane c is broadcast with readlane and subtracted from the rows below it.
+//
+// trsv_chain_kernel  one workgroup per batch item, everything in order.
+// trsv_coop_kernel   per batch item one critical workgroup and H helpers.
+//   Helpers stream the far list of later blocks at memory bandwidth and
+//   publish each block's partial sum.  The critical workgroup keeps the last
+//   two blocks of unknowns in an LDS ring: wave 0 sweeps block g while waves
+//   1-3 prefetch the triangle and the near list of block g+1 into LDS and
+//   compute its mid part; then all waves finish the near part of g+1.
+//   Communication: data that crosses workgroups is stored write-through
+//   (agent-coherent stores), followed by s_waitcnt and a flag store; readers
+//   poll flags with coherent loads and read published data with coherent
+//   loads, except unknowns two or more blocks behind the progress counter,
+//   whose cache lines can no longer hold unfinished rows.  Flags carry the
+//   launch's epoch, so nothing is reset between launches.  The launch is
+//   cooperative (all workgroups co-resident) and every wait is bounded: a
+//   timeout raises an abort flag that ends all waits.  All workgroups of a
+//   batch item are placed on one XCD (workgroup id mod 8) so that they share
+//   its L2.
+#include <cstdio>
+
 #include "common.hpp"
 #include "cplx.hpp"
+#include "kernels.hpp"
 #include "profile.hpp"
+#include "schedule.hpp"
 
 namespace omss {
 
@@ -27,13 +46,62 @@ __device__ inline float bcast(float v, int l) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
 }
 
-constexpr int TRSV_WAVES = 4;
+constexpr int TW = 4;              // waves per workgroup
+constexpr int TRI_N = 2016;        // packed strictly-lower 64x64
+constexpr int RING = NEAR_BLOCKS * 64;
+constexpr int NEAR_PF = 24;        // near slots of the next block staged in LDS
+constexpr int NXCD = 8;
+constexpr long long SPIN_LIMIT = 1ll << 22;
 
+// Column sweep of the unit-lower diagonal block (wave 0): r holds the right-
+// hand side of lane = row on entry and the unknown on exit.
 template <typename VT>
-__global__ __launch_bounds__(64 * TRSV_WAVES) void trsv_block_kernel(const TriView<VT>* __restrict__ views, int kind,
-                                                                      const VT* rhs, VT* out, int64_t n,
-                                                                      const int32_t* __restrict__ active) {
+__device__ inline VT sweep(VT r, const VT* tri, int lane) {
     using ST = typename Scalar<VT>::type;
+#pragma unroll 9
+    for (int c = 0; c < 63; ++c) {
+        const VT t = tri[c * 63 - (c * (c - 1)) / 2 + (lane > c ? lane - c - 1 : 0)];
+        const ST xr = bcast(r.x, c);
+        const ST xi = bcast(r.y, c);
+        if (lane > c) {
+            r.x -= t.x * xr;
+            r.x += t.y * xi;
+            r.y -= t.x * xi;
+            r.y -= t.y * xr;
+        }
+    }
+    return r;
+}
+
+// coherent (agent-scope) loads and write-through stores of complex values
+template <typename VT> __device__ inline VT ld_coh(const VT* p);
+template <> __device__ inline double2 ld_coh<double2>(const double2* p) {
+    const double* q = reinterpret_cast<const double*>(p);
+    return make_double2(__hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+                        __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+template <> __device__ inline float2 ld_coh<float2>(const float2* p) {
+    const float* q = reinterpret_cast<const float*>(p);
+    return make_float2(__hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+                       __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+template <typename VT> __device__ inline void st_wt(VT* p, VT v);
+template <> __device__ inline void st_wt<double2>(double2* p, double2 v) {
+    double* q = reinterpret_cast<double*>(p);
+    __hip_atomic_store(q, v.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(q + 1, v.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <> __device__ inline void st_wt<float2>(float2* p, float2 v) {
+    float* q = reinterpret_cast<float*>(p);
+    __hip_atomic_store(q, v.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(q + 1, v.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ---------------------------------------------------------------- single-workgroup chain
+template <typename VT>
+__global__ __launch_bounds__(64 * TW) void trsv_chain_kernel(const TriView<VT>* __restrict__ views, int kind,
+                                                              const VT* rhs, VT* out, int64_t n,
+                                                              const int32_t* __restrict__ active) {
     const int b = blockIdx.x;
     if (active && !active[b]) return;
     const TriView<VT> S = views[b * 4 + kind];
@@ -41,20 +109,22 @@ __global__ __launch_bounds__(64 * TRSV_WAVES) void trsv_block_kernel(const TriVi
     VT* x = out + (int64_t)b * n;
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
-    __shared__ VT part[TRSV_WAVES][64];
-    __shared__ VT tri[2016];
+    __shared__ VT part[TW][64];
+    __shared__ VT tri[TRI_N];
 
     for (int64_t g = 0; g < S.nblk; ++g) {
-        for (int t = threadIdx.x; t < 2016; t += 64 * TRSV_WAVES) tri[t] = S.dg[g * 2016 + t];
+        for (int t = threadIdx.x; t < TRI_N; t += 64 * TW) tri[t] = S.dg[g * TRI_N + t];
         VT acc = czero<VT>();
-        const int64_t s0 = S.off[g], s1 = S.off[g + 1];
+        for (int list = 0; list < 3; ++list) {
+            const int64_t* off = list == 0 ? S.far_off : list == 1 ? S.mid_off : S.near_off;
+            const int32_t* cl = list == 0 ? S.far_col : list == 1 ? S.mid_col : S.near_col;
+            const VT* vl = list == 0 ? S.far_val : list == 1 ? S.mid_val : S.near_val;
 #pragma unroll 4
-        for (int64_t s = s0 + wave; s < s1; s += TRSV_WAVES) {
-            const int64_t at = s * 64 + lane;
-            const int64_t c = S.col[at];
-            const VT v = S.val[at];
-            const VT xv = x[S.rev ? (n - 1 - c) : c];
-            cfma(acc, v, xv);
+            for (int64_t s = off[g] + wave; s < off[g + 1]; s += TW) {
+                const int64_t at = s * 64 + lane;
+                const int64_t c = cl[at];
+                cfma(acc, vl[at], x[S.rev ? (n - 1 - c) : c]);
+            }
         }
         part[wave][lane] = acc;
         __syncthreads();
@@ -68,23 +138,216 @@ __global__ __launch_bounds__(64 * TRSV_WAVES) void trsv_block_kernel(const TriVi
                 if (S.dinv) r = cmul(r, S.dinv[row]);
             }
 #pragma unroll
-            for (int w = 0; w < TRSV_WAVES; ++w) r = csub(r, part[w][lane]);
-            for (int c = 0; c < 63; ++c) {
-                const ST xr = bcast(r.x, c);
-                const ST xi = bcast(r.y, c);
-                if (lane > c) {
-                    const VT t = tri[c * 63 - (c * (c - 1)) / 2 + (lane - c - 1)];
-                    r.x -= t.x * xr;
-                    r.x += t.y * xi;
-                    r.y -= t.x * xi;
-                    r.y -= t.y * xr;
-                }
-            }
+            for (int w = 0; w < TW; ++w) r = csub(r, part[w][lane]);
+            r = sweep(r, tri, lane);
             if (valid) x[mi] = r;
         }
         __syncthreads();
     }
 }
+
+// ---------------------------------------------------------------- cooperative version
+struct CoopArgs {
+    double2* far_buf;     // batch * nblk * 64 values of VT (reinterpreted)
+    int32_t* fdone;       // batch * nblk
+    int64_t* progress;    // batch
+    int32_t* abort_flag;
+    uint32_t epoch;
+    int helpers;          // helper workgroups per item
+    int batch;
+    int per_xcd;          // workgroups per XCD per item slot = 1 + helpers
+    unsigned long long* tstat;   // diagnostics (nullable)
+};
+
+__device__ inline bool aborted(const int32_t* f) {
+    return __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+}
+
+__device__ inline void raise_abort(int32_t* f) {
+    __hip_atomic_store(f, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wait until *p >= target; returns the observed value or -1 on timeout/abort.
+__device__ inline int64_t wait_ge64(const int64_t* p, int64_t target, int32_t* abort_flag) {
+    long long spins = 0;
+    int64_t v;
+    while ((v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) < target) {
+        if (aborted(abort_flag)) return -1;
+        if (++spins > SPIN_LIMIT) { raise_abort(abort_flag); return -1; }
+        __builtin_amdgcn_s_sleep(1);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    return v;
+}
+
+__device__ inline bool wait_eq32(const int32_t* p, int32_t v, int32_t* abort_flag) {
+    long long spins = 0;
+    while (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != v) {
+        if (aborted(abort_flag)) return false;
+        if (++spins > SPIN_LIMIT) { raise_abort(abort_flag); return false; }
+        __builtin_amdgcn_s_sleep(1);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    return true;
+}
+
+template <typename VT>
+struct CoopShared {
+    VT tri[2][TRI_N];
+    VT near_v[NEAR_PF][64];
+    int32_t near_c[NEAR_PF][64];
+    VT part[TW][64];
+    VT mid[2][TW - 1][64];
+    VT ring[RING];
+    int fail;
+};
+
+template <typename VT>
+__global__ __launch_bounds__(64 * TW) void trsv_coop_kernel(const TriView<VT>* __restrict__ views, int kind,
+                                                             const VT* rhs, VT* out, int64_t n,
+                                                             const int32_t* __restrict__ active, CoopArgs a) {
+    // placement: workgroup w sits on XCD w % 8; item b uses XCD b % 8
+    const int xcd = blockIdx.x % NXCD;
+    const int q = blockIdx.x / NXCD;
+    const int b = xcd + NXCD * (q / a.per_xcd);
+    const int role = q % a.per_xcd;
+    if (b >= a.batch) return;
+    if (active && !active[b]) return;
+    const TriView<VT> S = views[b * 4 + kind];
+    VT* x = out + (int64_t)b * n;
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    VT* far_buf = reinterpret_cast<VT*>(a.far_buf) + (int64_t)b * S.nblk * 64;
+    int32_t* fdone = a.fdone + (int64_t)b * S.nblk;
+    int64_t* progress = a.progress + b;
+    const int64_t ep = (int64_t)a.epoch << 32;
+    __shared__ CoopShared<VT> sh;
+
+    if (role > 0) {
+        // ---- helper: far parts of blocks role-1, role-1+H, ...
+        int64_t known = 0;   // blocks finished in this epoch, as last observed
+        for (int64_t g = role - 1; g < S.nblk; g += a.helpers) {
+            VT acc = czero<VT>();
+            bool ok = true;
+            const int64_t s1 = S.far_off[g + 1];
+#pragma unroll 2
+            for (int64_t s = S.far_off[g] + wave; s < s1; s += TW) {
+                const int64_t need = S.far_need[s];
+                if (need + 2 > known) {
+                    const int64_t v = wait_ge64(progress, ep + need + 1, a.abort_flag);
+                    if (v < 0) { ok = false; break; }
+                    known = v - ep;
+                }
+                const int64_t at = s * 64 + lane;
+                const int64_t c = S.far_col[at];
+                const VT* px = x + (S.rev ? (n - 1 - c) : c);
+                // unknowns of the newest finished block may share a cache line with
+                // unfinished rows: read them coherently
+                const VT xv = (c >> 6) + 1 >= known ? ld_coh(px) : *px;
+                cfma(acc, S.far_val[at], xv);
+            }
+            sh.part[wave][lane] = acc;
+            if (__syncthreads_or(!ok)) return;
+            if (wave == 0) {
+                VT t = sh.part[0][lane];
+#pragma unroll
+                for (int w = 1; w < TW; ++w) t = cadd(t, sh.part[w][lane]);
+                st_wt(far_buf + g * 64 + lane, t);
+                __builtin_amdgcn_s_waitcnt(0);
+                if (lane == 0) __hip_atomic_store(fdone + g, (int32_t)a.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            __syncthreads();
+        }
+        return;
+    }
+
+    // ---- critical workgroup
+    const VT* y = rhs + (int64_t)b * n;
+    unsigned long long t_near = 0, t_wait = 0, t_sweep = 0, tA = 0;
+    // prologue: triangle and near list of block 0, mid(0) = 0
+    for (int t = threadIdx.x; t < TRI_N; t += 64 * TW) sh.tri[0][t] = S.dg[t];
+    {
+        const int64_t n0 = S.near_off[0], n1 = S.near_off[1];
+        for (int64_t s = n0 + wave; s < n1 && s - n0 < NEAR_PF; s += TW) {
+            sh.near_c[s - n0][lane] = S.near_col[s * 64 + lane];
+            sh.near_v[s - n0][lane] = S.near_val[s * 64 + lane];
+        }
+    }
+    if (wave > 0) sh.mid[0][wave - 1][lane] = czero<VT>();
+    if (threadIdx.x == 0) {
+        sh.fail = 0;
+        __hip_atomic_store(progress, ep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    for (int64_t g = 0; g < S.nblk; ++g) {
+        if (a.tstat && threadIdx.x == 0) tA = wall_clock64();
+        const int buf = (int)(g & 1);
+        // near part of block g (columns in block g-1), x from the ring
+        VT acc = czero<VT>();
+        {
+            const int64_t n0 = S.near_off[g], n1 = S.near_off[g + 1];
+            for (int64_t s = n0 + wave; s < n1; s += TW) {
+                const int64_t k = s - n0;
+                int32_t c;
+                VT v;
+                if (k < NEAR_PF) { c = sh.near_c[k][lane]; v = sh.near_v[k][lane]; }
+                else { c = S.near_col[s * 64 + lane]; v = S.near_val[s * 64 + lane]; }
+                cfma(acc, v, sh.ring[c & (RING - 1)]);
+            }
+        }
+        sh.part[wave][lane] = acc;
+        if (wave == 0 && lane == 0) {
+            const unsigned long long tB = a.tstat ? wall_clock64() : 0;
+            if (!wait_eq32(fdone + g, (int32_t)a.epoch, a.abort_flag)) sh.fail = 1;
+            if (a.tstat) { const unsigned long long tC = wall_clock64(); t_near += tB - tA; t_wait += tC - tB; tA = tC; }
+        }
+        __syncthreads();
+        if (sh.fail) return;
+        if (wave == 0) {
+            const int64_t row = g * 64 + lane;
+            const bool valid = row < n;
+            const int64_t mi = S.rev ? (n - 1 - row) : row;
+            VT r = czero<VT>();
+            if (valid) {
+                r = y[mi];
+                if (S.dinv) r = cmul(r, S.dinv[row]);
+            }
+            r = csub(r, ld_coh(far_buf + g * 64 + lane));
+#pragma unroll
+            for (int w = 0; w < TW; ++w) r = csub(r, sh.part[w][lane]);
+#pragma unroll
+            for (int w = 0; w < TW - 1; ++w) r = csub(r, sh.mid[buf][w][lane]);
+            r = sweep(r, sh.tri[buf], lane);
+            sh.ring[(g * 64 + lane) & (RING - 1)] = r;
+            if (valid) st_wt(x + mi, r);
+            __builtin_amdgcn_s_waitcnt(0);
+            if (lane == 0) __hip_atomic_store(progress, ep + g + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (a.tstat && lane == 0) t_sweep += wall_clock64() - tA;
+        } else if (g + 1 < S.nblk) {
+            // waves 1-3: stage block g+1 and compute its mid part (block g-1, in the ring)
+            const int64_t g1 = g + 1;
+            for (int t = threadIdx.x - 64; t < TRI_N; t += 64 * (TW - 1)) sh.tri[buf ^ 1][t] = S.dg[g1 * TRI_N + t];
+            const int64_t n0 = S.near_off[g1], n1 = S.near_off[g1 + 1];
+            for (int64_t s = n0 + wave - 1; s < n1 && s - n0 < NEAR_PF; s += TW - 1) {
+                sh.near_c[s - n0][lane] = S.near_col[s * 64 + lane];
+                sh.near_v[s - n0][lane] = S.near_val[s * 64 + lane];
+            }
+            VT m = czero<VT>();
+            const int64_t m0 = S.mid_off[g1], m1 = S.mid_off[g1 + 1];
+            for (int64_t s = m0 + wave - 1; s < m1; s += TW - 1)
+                cfma(m, S.mid_val[s * 64 + lane], sh.ring[S.mid_col[s * 64 + lane] & (RING - 1)]);
+            sh.mid[buf ^ 1][wave - 1][lane] = m;
+        }
+        __syncthreads();
+    }
+    if (a.tstat && threadIdx.x == 0) {
+        atomicAdd(a.tstat + 0, t_near);
+        atomicAdd(a.tstat + 1, t_wait);
+        atomicAdd(a.tstat + 2, t_sweep);
+    }
+}
+
+// ---------------------------------------------------------------- launch
 
 // Algorithmic bytes of one triangular solve over the active items: values and
 // column indices of the factor, right-hand side read, solution written, and
@@ -99,19 +362,77 @@ static double trsv_bytes(const om_ilu* M, int kind, size_t s, const int32_t* act
     return b;
 }
 
+static bool use_chain() {
+    const char* e = getenv("OMSS_TRSV");
+    return e && e[0] == 'c' && e[1] == 'h';   // "chain" forces the single-workgroup kernel
+}
+
 template <typename VT>
-om_status launch_trsv(const om_ilu* M, const TriView<VT>* views, int kind, const VT* rhs, VT* out,
-                      const int32_t* active, const int32_t* act_host, hipStream_t s) {
+static om_status launch_trsv(om_ilu* M, const TriView<VT>* views, int kind, const VT* rhs, VT* out,
+                             const int32_t* active, const int32_t* act_host, hipStream_t s) {
     ProfScope prof("trsv", s, profile_enabled() ? trsv_bytes(M, kind, sizeof(VT), act_host) : 0.0);
-    hipLaunchKernelGGL(trsv_block_kernel<VT>, dim3(M->batch), dim3(64 * TRSV_WAVES), 0, s, views, kind, rhs, out, M->n,
-                       active);
+    const int B = M->batch;
+    if (!use_chain()) {
+        static int maxgrid[2] = {0, 0};
+        int& mg = maxgrid[sizeof(VT) == sizeof(double2)];
+        if (mg == 0) {
+            int dev = 0, cus = 0, per = 0, coop = 0;
+            OM_HIP(hipGetDevice(&dev));
+            OM_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+            OM_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
+            OM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, trsv_coop_kernel<VT>, 64 * TW, 0));
+            mg = coop ? cus * per : -1;
+        }
+        const int64_t nblk = (M->n + 63) / 64;
+        const int slots = (B + NXCD - 1) / NXCD;   // items per XCD
+        int H = 0;
+        if (mg > 0) {
+            const char* e = getenv("OMSS_TRSV_HELPERS");
+            H = e ? atoi(e) : 16;
+            H = (int)std::min<int64_t>(H, nblk);
+            H = std::min(H, mg / (NXCD * slots) - 1);
+        }
+        if (H >= 1) {
+            CoopArgs a;
+            a.far_buf = M->scratch.far_buf.p;
+            a.fdone = M->scratch.fdone.p;
+            a.progress = M->scratch.progress.p;
+            a.abort_flag = M->scratch.abort_flag.p;
+            a.epoch = ++M->scratch.epoch;
+            if (a.epoch == 0) a.epoch = ++M->scratch.epoch;
+            a.helpers = H;
+            a.batch = B;
+            a.per_xcd = 1 + H;
+            static unsigned long long* tst = nullptr;
+            a.tstat = nullptr;
+            if (getenv("OMSS_TRSV_STATS")) {
+                if (!tst) OM_HIP(hipMalloc((void**)&tst, 3 * sizeof(unsigned long long)));
+                OM_HIP(hipMemsetAsync(tst, 0, 3 * sizeof(unsigned long long), s));
+                a.tstat = tst;
+            }
+            int64_t n = M->n;
+            void* args[] = {(void*)&views, (void*)&kind, (void*)&rhs, (void*)&out, (void*)&n, (void*)&active, (void*)&a};
+            OM_HIP(hipLaunchCooperativeKernel((const void*)trsv_coop_kernel<VT>, dim3(NXCD * slots * (1 + H)),
+                                              dim3(64 * TW), args, 0, s));
+            if (a.tstat) {
+                unsigned long long h[3];
+                OM_HIP(hipMemcpyAsync(h, a.tstat, sizeof h, hipMemcpyDeviceToHost, s));
+                OM_HIP(hipStreamSynchronize(s));
+                fprintf(stderr, "[trsv stats] H=%d kind=%d per item: near %.3f ms, wait %.3f ms, sweep+stage %.3f ms\n", H,
+                        kind, h[0] / 1e5 / B, h[1] / 1e5 / B, h[2] / 1e5 / B);
+            }
+            return OM_OK;
+        }
+    }
+    hipLaunchKernelGGL(trsv_chain_kernel<VT>, dim3(B), dim3(64 * TW), 0, s, views, kind, rhs, out, M->n, active);
     OM_HIP(hipGetLastError());
     return OM_OK;
 }
 
 // y = (L U)^{-1} x or (L U)^{-H} x for every active batch item; x, y may alias.
-om_status ilu_apply_dev(const om_ilu* M, int adjoint, int dtype, const void* x, void* y, const int32_t* active,
+om_status ilu_apply_dev(const om_ilu* Mc, int adjoint, int dtype, const void* x, void* y, const int32_t* active,
                         hipStream_t s, const int32_t* act_host) {
+    om_ilu* M = const_cast<om_ilu*>(Mc);
     const int k0 = adjoint ? 2 : 0, k1 = adjoint ? 3 : 1;
     if (dtype == OM_C128) {
         OM_TRY(launch_trsv<double2>(M, M->views64.p, k0, (const double2*)x, (double2*)y, active, act_host, s));
@@ -119,6 +440,23 @@ om_status ilu_apply_dev(const om_ilu* M, int adjoint, int dtype, const void* x, 
     } else {
         OM_TRY(launch_trsv<float2>(M, M->views32.p, k0, (const float2*)x, (float2*)y, active, act_host, s));
         OM_TRY(launch_trsv<float2>(M, M->views32.p, k1, (const float2*)y, (float2*)y, active, act_host, s));
+    }
+    return OM_OK;
+}
+
+// OM_ETIMEOUT if a bounded wait of a cooperative solve expired since the last
+// check (the flag is cleared).
+om_status trsv_check(const om_ilu* Mc, hipStream_t s) {
+    om_ilu* M = const_cast<om_ilu*>(Mc);
+    if (!M->scratch.abort_flag.p) return OM_OK;
+    int32_t f = 0;
+    OM_HIP(hipMemcpyAsync(&f, M->scratch.abort_flag.p, sizeof f, hipMemcpyDeviceToHost, s));
+    OM_HIP(hipStreamSynchronize(s));
+    if (f) {
+        OM_HIP(hipMemsetAsync(M->scratch.abort_flag.p, 0, sizeof f, s));
+        OM_HIP(hipStreamSynchronize(s));
+        set_error("a triangular solve timed out waiting for its helpers (abort flag set)");
+        return OM_ETIMEOUT;
     }
     return OM_OK;
 }
