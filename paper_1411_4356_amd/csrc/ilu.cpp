@@ -77,14 +77,21 @@ om_status ilu_factor_impl(const om_csr* Ain, double drop_tol, double fill_factor
     std::vector<om_status> status(B, OM_OK);
     std::vector<std::string> errs(B);
     std::vector<int64_t> nl(B), nu(B), dl(B), du(B), rep(B);
-    const int T = std::max(1, std::min(B, host_threads()));
+    // items run concurrently, each with its share of the host threads
+    const int HT = host_threads();
+    const int T = std::max(1, std::min(B, HT));
+    const int per_item = std::max(1, HT / T);
     auto work = [&](int t) {
         (void)hipSetDevice(dev);
         for (int b = t; b < B; b += T) {
             std::unique_ptr<HostFactor> F(new HostFactor);
             std::string err;
-            if (ilut_factor_host(n, A->h_row_ptr.data(), A->h_col.data(), vals.data() + (size_t)b * nnz * 2, drop_tol,
-                                 fill_factor, 0.0, F.get(), &err) != 0) {
+            const int rc = per_item > 1
+                ? ilut_factor_host_mt(n, A->h_row_ptr.data(), A->h_col.data(), vals.data() + (size_t)b * nnz * 2,
+                                      drop_tol, fill_factor, per_item, F.get(), &err)
+                : ilut_factor_host(n, A->h_row_ptr.data(), A->h_col.data(), vals.data() + (size_t)b * nnz * 2,
+                                   drop_tol, fill_factor, 0.0, F.get(), &err);
+            if (rc != 0) {
                 status[b] = OM_EBREAKDOWN;
                 errs[b] = "batch item " + std::to_string(b) + ": " + err;
                 continue;
@@ -157,7 +164,10 @@ om_status host_ilut_impl(int64_t n, const int64_t* row_ptr, const int32_t* col, 
     M->host.resize(1);
     M->host[0].reset(new HostFactor);
     std::string err;
-    if (ilut_factor_host(n, row_ptr, col, val, drop_tol, fill_factor, 0.0, M->host[0].get(), &err) != 0) {
+    const int HT = host_threads();
+    const int rc = HT > 1 ? ilut_factor_host_mt(n, row_ptr, col, val, drop_tol, fill_factor, HT, M->host[0].get(), &err)
+                          : ilut_factor_host(n, row_ptr, col, val, drop_tol, fill_factor, 0.0, M->host[0].get(), &err);
+    if (rc != 0) {
         set_error("%s", err.c_str());
         return OM_EBREAKDOWN;
     }

@@ -21,4 +21,9 @@ struct HostFactor {
 int ilut_factor_host(int64_t n, const int64_t* row_ptr, const int32_t* col, const double* val,
                      double drop_tol, double fill_factor, double permtol, HostFactor* out, std::string* err);
 
+// Row-pipelined multi-threaded version (no pivoting): identical factor,
+// `threads` host threads.  Returns 0 on success, 1 on breakdown (err set).
+int ilut_factor_host_mt(int64_t n, const int64_t* row_ptr, const int32_t* col, const double* val,
+                        double drop_tol, double fill_factor, int threads, HostFactor* out, std::string* err);
+
 }  // namespace omss

@@ -49,8 +49,9 @@ __device__ inline float bcast(float v, int l) {
 constexpr int TW = 4;              // waves per workgroup
 constexpr int TRI_N = 2016;        // packed strictly-lower 64x64
 constexpr int RING = NEAR_BLOCKS * 64;
-constexpr int NEAR_PF = 24;        // near slots of the next block staged in LDS
+constexpr int NEAR_PF = 64;        // near slots of the next block staged in LDS (all: a row has at most 64 entries in the previous block)
 constexpr int NXCD = 8;
+constexpr int FU = 8;               // slots per wave per chunk in the streamed loops
 constexpr long long SPIN_LIMIT = 1ll << 22;
 
 // Column sweep of the unit-lower diagonal block (wave 0): r holds the right-
@@ -113,17 +114,36 @@ __global__ __launch_bounds__(64 * TW) void trsv_chain_kernel(const TriView<VT>* 
     __shared__ VT tri[TRI_N];
 
     for (int64_t g = 0; g < S.nblk; ++g) {
-        for (int t = threadIdx.x; t < TRI_N; t += 64 * TW) tri[t] = S.dg[g * TRI_N + t];
+        {
+            constexpr int TPER = (TRI_N + 64 * TW - 1) / (64 * TW);
+            VT tv[TPER];
+#pragma unroll
+            for (int j = 0; j < TPER; ++j)
+                if (threadIdx.x + j * 64 * TW < TRI_N) tv[j] = S.dg[g * TRI_N + threadIdx.x + j * 64 * TW];
+#pragma unroll
+            for (int j = 0; j < TPER; ++j)
+                if (threadIdx.x + j * 64 * TW < TRI_N) tri[threadIdx.x + j * 64 * TW] = tv[j];
+        }
         VT acc = czero<VT>();
         for (int list = 0; list < 3; ++list) {
             const int64_t* off = list == 0 ? S.far_off : list == 1 ? S.mid_off : S.near_off;
             const int32_t* cl = list == 0 ? S.far_col : list == 1 ? S.mid_col : S.near_col;
             const VT* vl = list == 0 ? S.far_val : list == 1 ? S.mid_val : S.near_val;
-#pragma unroll 4
-            for (int64_t s = off[g] + wave; s < off[g + 1]; s += TW) {
-                const int64_t at = s * 64 + lane;
-                const int64_t c = cl[at];
-                cfma(acc, vl[at], x[S.rev ? (n - 1 - c) : c]);
+            const int64_t e1 = off[g + 1];
+            for (int64_t c0 = off[g] + (int64_t)wave * FU; c0 < e1; c0 += (int64_t)TW * FU) {
+                const int cnt = (int)(e1 - c0 < FU ? e1 - c0 : FU);
+                int32_t cc[FU];
+                VT vv[FU];
+#pragma unroll
+                for (int j = 0; j < FU; ++j)
+                    if (j < cnt) { cc[j] = cl[(c0 + j) * 64 + lane]; vv[j] = vl[(c0 + j) * 64 + lane]; }
+                VT xv[FU];
+#pragma unroll
+                for (int j = 0; j < FU; ++j)
+                    if (j < cnt) xv[j] = x[S.rev ? (n - 1 - cc[j]) : cc[j]];
+#pragma unroll
+                for (int j = 0; j < FU; ++j)
+                    if (j < cnt) cfma(acc, vv[j], xv[j]);
             }
         }
         part[wave][lane] = acc;
@@ -230,21 +250,40 @@ __global__ __launch_bounds__(64 * TW) void trsv_coop_kernel(const TriView<VT>* _
             VT acc = czero<VT>();
             bool ok = true;
             const int64_t s1 = S.far_off[g + 1];
-#pragma unroll 2
-            for (int64_t s = S.far_off[g] + wave; s < s1; s += TW) {
-                const int64_t need = S.far_need[s];
-                if (need + 2 > known) {
-                    const int64_t v = wait_ge64(progress, ep + need + 1, a.abort_flag);
+            // chunks of FU consecutive slots per wave: one progress check per chunk,
+            // all column/value loads of the chunk issued before the gathers
+            for (int64_t c0 = S.far_off[g] + (int64_t)wave * FU; c0 < s1; c0 += (int64_t)TW * FU) {
+                const int cnt = (int)(s1 - c0 < FU ? s1 - c0 : FU);
+                int64_t needmax = 0;
+#pragma unroll
+                for (int j = 0; j < FU; ++j)
+                    if (j < cnt) needmax = needmax > S.far_need[c0 + j] ? needmax : (int64_t)S.far_need[c0 + j];
+                if (needmax + 2 > known) {
+                    const int64_t v = wait_ge64(progress, ep + needmax + 1, a.abort_flag);
                     if (v < 0) { ok = false; break; }
                     known = v - ep;
                 }
-                const int64_t at = s * 64 + lane;
-                const int64_t c = S.far_col[at];
-                const VT* px = x + (S.rev ? (n - 1 - c) : c);
-                // unknowns of the newest finished block may share a cache line with
-                // unfinished rows: read them coherently
-                const VT xv = (c >> 6) + 1 >= known ? ld_coh(px) : *px;
-                cfma(acc, S.far_val[at], xv);
+                int32_t cc[FU];
+                VT vv[FU];
+#pragma unroll
+                for (int j = 0; j < FU; ++j)
+                    if (j < cnt) {
+                        cc[j] = S.far_col[(c0 + j) * 64 + lane];
+                        vv[j] = S.far_val[(c0 + j) * 64 + lane];
+                    }
+                VT xv[FU];
+#pragma unroll
+                for (int j = 0; j < FU; ++j)
+                    if (j < cnt) {
+                        const int64_t c = cc[j];
+                        const VT* px = x + (S.rev ? (n - 1 - c) : c);
+                        // unknowns of the newest finished block may share a cache line
+                        // with unfinished rows: read them coherently
+                        xv[j] = (c >> 6) + 1 >= known ? ld_coh(px) : *px;
+                    }
+#pragma unroll
+                for (int j = 0; j < FU; ++j)
+                    if (j < cnt) cfma(acc, vv[j], xv[j]);
             }
             sh.part[wave][lane] = acc;
             if (__syncthreads_or(!ok)) return;
@@ -286,13 +325,18 @@ __global__ __launch_bounds__(64 * TW) void trsv_coop_kernel(const TriView<VT>* _
         VT acc = czero<VT>();
         {
             const int64_t n0 = S.near_off[g], n1 = S.near_off[g + 1];
-            for (int64_t s = n0 + wave; s < n1; s += TW) {
-                const int64_t k = s - n0;
-                int32_t c;
-                VT v;
-                if (k < NEAR_PF) { c = sh.near_c[k][lane]; v = sh.near_v[k][lane]; }
-                else { c = S.near_col[s * 64 + lane]; v = S.near_val[s * 64 + lane]; }
-                cfma(acc, v, sh.ring[c & (RING - 1)]);
+            const int64_t nl = n1 - n0 < NEAR_PF ? n1 - n0 : NEAR_PF;
+            for (int64_t k = wave; k < nl; k += TW) cfma(acc, sh.near_v[k][lane], sh.ring[sh.near_c[k][lane] & (RING - 1)]);
+            for (int64_t c0 = n0 + NEAR_PF + (int64_t)wave * FU; c0 < n1; c0 += (int64_t)TW * FU) {
+                const int cnt = (int)(n1 - c0 < FU ? n1 - c0 : FU);
+                int32_t cc[FU];
+                VT vv[FU];
+#pragma unroll
+                for (int j = 0; j < FU; ++j)
+                    if (j < cnt) { cc[j] = S.near_col[(c0 + j) * 64 + lane]; vv[j] = S.near_val[(c0 + j) * 64 + lane]; }
+#pragma unroll
+                for (int j = 0; j < FU; ++j)
+                    if (j < cnt) cfma(acc, vv[j], sh.ring[cc[j] & (RING - 1)]);
             }
         }
         sh.part[wave][lane] = acc;
@@ -326,16 +370,49 @@ __global__ __launch_bounds__(64 * TW) void trsv_coop_kernel(const TriView<VT>* _
         } else if (g + 1 < S.nblk) {
             // waves 1-3: stage block g+1 and compute its mid part (block g-1, in the ring)
             const int64_t g1 = g + 1;
-            for (int t = threadIdx.x - 64; t < TRI_N; t += 64 * (TW - 1)) sh.tri[buf ^ 1][t] = S.dg[g1 * TRI_N + t];
-            const int64_t n0 = S.near_off[g1], n1 = S.near_off[g1 + 1];
-            for (int64_t s = n0 + wave - 1; s < n1 && s - n0 < NEAR_PF; s += TW - 1) {
-                sh.near_c[s - n0][lane] = S.near_col[s * 64 + lane];
-                sh.near_v[s - n0][lane] = S.near_val[s * 64 + lane];
+            constexpr int TPER = (TRI_N + 64 * (TW - 1) - 1) / (64 * (TW - 1));
+            {
+                VT tv[TPER];
+#pragma unroll
+                for (int j = 0; j < TPER; ++j) {
+                    const int t = threadIdx.x - 64 + j * 64 * (TW - 1);
+                    if (t < TRI_N) tv[j] = S.dg[g1 * TRI_N + t];
+                }
+#pragma unroll
+                for (int j = 0; j < TPER; ++j) {
+                    const int t = threadIdx.x - 64 + j * 64 * (TW - 1);
+                    if (t < TRI_N) sh.tri[buf ^ 1][t] = tv[j];
+                }
+            }
+            {
+                const int64_t n0 = S.near_off[g1], n1 = S.near_off[g1 + 1];
+                constexpr int NPER = (NEAR_PF + TW - 2) / (TW - 1);
+                int32_t nc[NPER];
+                VT nv[NPER];
+#pragma unroll
+                for (int j = 0; j < NPER; ++j) {
+                    const int64_t s = n0 + (wave - 1) + (int64_t)j * (TW - 1);
+                    if (s < n1 && s - n0 < NEAR_PF) { nc[j] = S.near_col[s * 64 + lane]; nv[j] = S.near_val[s * 64 + lane]; }
+                }
+#pragma unroll
+                for (int j = 0; j < NPER; ++j) {
+                    const int64_t s = n0 + (wave - 1) + (int64_t)j * (TW - 1);
+                    if (s < n1 && s - n0 < NEAR_PF) { sh.near_c[s - n0][lane] = nc[j]; sh.near_v[s - n0][lane] = nv[j]; }
+                }
             }
             VT m = czero<VT>();
             const int64_t m0 = S.mid_off[g1], m1 = S.mid_off[g1 + 1];
-            for (int64_t s = m0 + wave - 1; s < m1; s += TW - 1)
-                cfma(m, S.mid_val[s * 64 + lane], sh.ring[S.mid_col[s * 64 + lane] & (RING - 1)]);
+            for (int64_t c0 = m0 + (int64_t)(wave - 1) * FU; c0 < m1; c0 += (int64_t)(TW - 1) * FU) {
+                const int cnt = (int)(m1 - c0 < FU ? m1 - c0 : FU);
+                int32_t cc[FU];
+                VT vv[FU];
+#pragma unroll
+                for (int j = 0; j < FU; ++j)
+                    if (j < cnt) { cc[j] = S.mid_col[(c0 + j) * 64 + lane]; vv[j] = S.mid_val[(c0 + j) * 64 + lane]; }
+#pragma unroll
+                for (int j = 0; j < FU; ++j)
+                    if (j < cnt) cfma(m, vv[j], sh.ring[cc[j] & (RING - 1)]);
+            }
             sh.mid[buf ^ 1][wave - 1][lane] = m;
         }
         __syncthreads();

@@ -111,3 +111,32 @@ def test_host_entry_points_reject_bad_input(P):
         P.host_ilut(A, 1e-3, 0.0)
     with pytest.raises(OmError):
         P.host_rcm(np.array([0, 1]), np.array([5]))
+
+
+@pytest.mark.parametrize("threads", ["1", "3", "8"])
+def test_host_ilut_threads_bit_identical(P, threads, monkeypatch):
+    """The row-pipelined multi-threaded factorisation gives the same factor,
+    bit for bit, as the sequential one (and as the oracle's pattern)."""
+    p = W.BATCH_BASE.replace(nc=4, nm=9)
+    Lt, _, _ = model.constrained_system(model.liouvillian(p))
+    A = ordering.permute(Lt, ordering.rcm(Lt))
+    monkeypatch.setenv("OMSS_HOST_THREADS", "1")
+    L1, U1, s1 = P.host_ilut(A, 1e-6, 20.0)
+    monkeypatch.setenv("OMSS_HOST_THREADS", threads)
+    L2, U2, s2 = P.host_ilut(A, 1e-6, 20.0)
+    for X, Y in ((L1, L2), (U1, U2)):
+        assert np.array_equal(X.indptr, Y.indptr) and np.array_equal(X.indices, Y.indices)
+        assert np.array_equal(X.data, Y.data)
+    Lo, Uo, _ = oilut.ilut(A, 1e-6, 20.0)
+    assert np.array_equal(L2.indices, Lo.indices) and np.array_equal(U2.indices, Uo.indices)
+
+
+def test_host_ilut_reports_breakdown(P):
+    """An unstable incomplete factorisation (too little fill) is reported as
+    breakdown rather than returned with non-finite entries."""
+    from paper_1411_4356_amd._lib import OmError, OM_EBREAKDOWN
+    A = sp.csr_matrix(np.array([[1e-300, 1.0, 0.0], [1.0, 1e-300, 1.0], [0.0, 1.0, 1e-300]], dtype=np.complex128))
+    A = sp.csr_matrix(np.array([[1.0, 1e300, 0.0], [1e300, 1.0, 1e300], [0.0, 1e300, 1.0]], dtype=np.complex128))
+    with pytest.raises(OmError) as e:
+        P.host_ilut(A, 0.0, float("inf"))
+    assert e.value.status == OM_EBREAKDOWN
