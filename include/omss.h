@@ -114,6 +114,7 @@ typedef struct {
     int32_t nth0_fix;       /* n_th == 0 is built as n_th = 1e-15 (Sec. IV) */
     int32_t reorder;        /* 1 = RCM (default), 0 = natural order */
     int32_t want_adjoint;   /* keep conjugate-transposed factors for adjoint solves */
+    int32_t share_factor;   /* one ILU factor (of item 0) preconditions the whole batch */
 } om_ss_opts;
 
 typedef struct {
@@ -191,12 +192,16 @@ om_status csr_permute(const om_csr* A, const int32_t* perm_host, om_csr** A_perm
  *        OM_ILU_ADJOINT keeps the conjugate-transposed factors;
  *        OM_ILU_CONDEST fills st->condest;
  *        OM_ILU_KEEP_HOST keeps a host copy of the CSR factors for
- *        om_ilu_export (costs host memory of the size of the factors).
+ *        om_ilu_export (costs host memory of the size of the factors);
+ *        OM_ILU_SHARED factors batch item 0 only (with all host threads) and
+ *        uses that factor as the preconditioner of every batch item (items
+ *        that differ only in parameter values share one structure).
  * Errors: OM_EINVAL (drop_tol < 0, fill_factor <= 0), OM_ENOMEM. */
 #define OM_ILU_C64 1u
 #define OM_ILU_ADJOINT 2u
 #define OM_ILU_CONDEST 4u
 #define OM_ILU_KEEP_HOST 8u
+#define OM_ILU_SHARED 16u
 om_status ilu_factor(const om_csr* A, double drop_tol, double fill_factor, uint32_t flags,
                      om_ilu** M_out, om_ilu_stats* st, void* stream);
 

@@ -14,7 +14,7 @@ OM_C128, OM_C64 = 0, 1
 OM_TRACE_NONE, OM_TRACE_REPLACE_ROW0, OM_TRACE_ADD_ROW0 = 0, 1, 2
 OM_PREC_FP64, OM_PREC_IR_C64 = 0, 1
 OM_BUILD_C64 = 1
-OM_ILU_C64, OM_ILU_ADJOINT, OM_ILU_CONDEST, OM_ILU_KEEP_HOST = 1, 2, 4, 8
+OM_ILU_C64, OM_ILU_ADJOINT, OM_ILU_CONDEST, OM_ILU_KEEP_HOST, OM_ILU_SHARED = 1, 2, 4, 8, 16
 
 
 class om_params(C.Structure):
@@ -47,7 +47,7 @@ class om_gmres_info(C.Structure):
 class om_ss_opts(C.Structure):
     _fields_ = [("drop_tol", C.c_double), ("fill_factor", C.c_double), ("gmres", om_gmres_opts),
                 ("trace_mode", C.c_int32), ("nth0_fix", C.c_int32), ("reorder", C.c_int32),
-                ("want_adjoint", C.c_int32)]
+                ("want_adjoint", C.c_int32), ("share_factor", C.c_int32)]
 
 
 class om_ss_info(C.Structure):
@@ -87,6 +87,9 @@ SIGNATURES = {
     "steady_state": (C.c_int, [C.POINTER(om_params), _i32, C.POINTER(om_ss_opts), _P, C.POINTER(om_ss_info),
                                C.POINTER(om_ss_results), _P]),
     "om_ss_opts_default": (None, [C.POINTER(om_ss_opts)]),
+    "om_profile_enable": (None, [C.c_int32]),
+    "om_profile_reset": (None, []),
+    "om_profile_query": (C.c_int, [C.c_char_p, C.POINTER(C.c_int64), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "om_observables": (C.c_int, [_P, _P, _dp, _P]),
     "om_objective_vectors": (C.c_int, [_P, _P, _P, _P]),
     "om_param_gradient": (C.c_int, [_P, _P, _P, _i32, _dp, _P]),

@@ -143,9 +143,10 @@ def csr_permute(A: Csr, perm, stream=None):
 
 
 def ilu_factor(A: Csr, drop_tol: float, fill_factor: float, c64: bool = False, adjoint: bool = False,
-               condest: bool = False, keep_host: bool = False, stream=None) -> Ilu:
+               condest: bool = False, keep_host: bool = False, shared: bool = False, stream=None) -> Ilu:
     flags = ((L.OM_ILU_C64 if c64 else 0) | (L.OM_ILU_ADJOINT if adjoint else 0)
-             | (L.OM_ILU_CONDEST if condest else 0) | (L.OM_ILU_KEEP_HOST if keep_host else 0))
+             | (L.OM_ILU_CONDEST if condest else 0) | (L.OM_ILU_KEEP_HOST if keep_host else 0)
+             | (L.OM_ILU_SHARED if shared else 0))
     h = C.c_void_p()
     st = L.om_ilu_stats()
     check(lib().ilu_factor(A.h, float(drop_tol), float(fill_factor), flags, C.byref(h), C.byref(st), _stream(stream)))
@@ -211,7 +212,7 @@ def default_ss_opts() -> L.om_ss_opts:
 def steady_state(params, drop_tol: float = 1e-6, fill_factor: float = 60.0, m: int = 50, tol: float = 1e-10,
                  maxiter: int = 1000, precision: str = "fp64", inner_tol: float = 1e-5, max_outer: int = 20,
                  trace_mode: int = L.OM_TRACE_REPLACE_ROW0, nth0_fix: bool = True, reorder: bool = True,
-                 allow_notconv: bool = False, stream=None):
+                 share_factor: bool = False, allow_notconv: bool = False, stream=None):
     """rho (complex128 [batch, N, N] on the device, rho[b][k, l]), info dict and
     per-item results (trace_err, herm_err, n_a, n_b, fano, relres)."""
     arr, nb = _params_array(params)
@@ -221,6 +222,7 @@ def steady_state(params, drop_tol: float = 1e-6, fill_factor: float = 60.0, m: i
     o.gmres = GmresOpts(m=m, maxiter=maxiter, tol=tol, precision=precision, inner_tol=inner_tol,
                         max_outer=max_outer).c()
     o.trace_mode, o.nth0_fix, o.reorder = trace_mode, int(nth0_fix), int(reorder)
+    o.share_factor = int(share_factor)
     # column-major N x N per item: element (k, l) at l*N + k
     rho_cm = torch.empty((nb, N, N), dtype=torch.complex128, device="cuda")
     info = L.om_ss_info()

@@ -202,7 +202,7 @@ om_status ilu_factor(const om_csr* A, double drop_tol, double fill_factor, uint3
 om_status om_ilu_info(const om_ilu* M, int32_t b, int64_t* n, int64_t* nnz_L, int64_t* nnz_U) {
     if (!M || b < 0 || b >= M->batch) { set_error("bad handle or item"); return OM_EINVAL; }
     if (n) *n = M->n;
-    const HostFactor* F = M->host[b].get();
+    const HostFactor* F = M->host[M->shared ? 0 : b].get();
     if (nnz_L) *nnz_L = F ? (int64_t)F->l_col.size() : -1;
     if (nnz_U) *nnz_U = F ? (int64_t)F->u_col.size() : -1;
     return OM_OK;
@@ -211,7 +211,7 @@ om_status om_ilu_info(const om_ilu* M, int32_t b, int64_t* n, int64_t* nnz_L, in
 om_status om_ilu_export(const om_ilu* M, int32_t b, int64_t* l_ptr, int32_t* l_col, double* l_val, int64_t* u_ptr,
                         int32_t* u_col, double* u_val) {
     if (!M || b < 0 || b >= M->batch) { set_error("bad handle or item"); return OM_EINVAL; }
-    const HostFactor* F = M->host[b].get();
+    const HostFactor* F = M->host[M->shared ? 0 : b].get();
     if (!F) { set_error("factors were not kept on the host (use OM_ILU_KEEP_HOST)"); return OM_EINVAL; }
     if (l_ptr) std::memcpy(l_ptr, F->l_ptr.data(), F->l_ptr.size() * sizeof(int64_t));
     if (l_col) std::memcpy(l_col, F->l_col.data(), F->l_col.size() * sizeof(int32_t));
@@ -310,7 +310,8 @@ om_status steady_state(const om_params* params, int32_t batch, const om_ss_opts*
         I.t_rcm_s = secs_since(t);
         t = std::chrono::steady_clock::now();
         om_ilu* M0 = nullptr;
-        uint32_t fl = (ir ? OM_ILU_C64 : 0u) | (opts->want_adjoint ? OM_ILU_ADJOINT : 0u);
+        uint32_t fl = (ir ? OM_ILU_C64 : 0u) | (opts->want_adjoint ? OM_ILU_ADJOINT : 0u) |
+                      (opts->share_factor ? OM_ILU_SHARED : 0u);
         OM_TRY(ilu_factor(A.get(), opts->drop_tol, opts->fill_factor, fl, &M0, &I.ilu, stream));
         std::unique_ptr<om_ilu, void (*)(om_ilu*)> M(M0, om_ilu_free);
         I.t_factor_s = secs_since(t);

@@ -165,9 +165,10 @@ struct om_ilu {
     int32_t batch = 0;
     uint32_t flags = 0;
     bool host_only = false;
-    std::vector<std::unique_ptr<omss::HostFactor>> host;   // per batch item
-    // per batch item: 0 = L, 1 = U (reversed, scaled), 2 = U^H (scaled), 3 = L^H (reversed)
-    std::vector<omss::TriSched> sched;                     // batch * 4
+    bool shared = false;   // one factor (of item 0) serves every batch item
+    std::vector<std::unique_ptr<omss::HostFactor>> host;   // per factor (1 if shared)
+    // per factor: 0 = L, 1 = U (reversed, scaled), 2 = U^H (scaled), 3 = L^H (reversed)
+    std::vector<omss::TriSched> sched;                     // factors * 4
     omss::DevBuf<omss::TriView<double2>> views64;          // batch * 4
     omss::DevBuf<omss::TriView<float2>> views32;           // batch * 4
     omss::TrsvScratch scratch;

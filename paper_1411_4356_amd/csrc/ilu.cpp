@@ -2,6 +2,9 @@
 // schedules, upload of the factors to the device.
 #include <algorithm>
 #include <chrono>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
 #include <cmath>
 #include <mutex>
 #include <string>
@@ -22,7 +25,7 @@ static om_status finish_views(om_ilu* M, hipStream_t s) {
     std::vector<TriView<float2>> v32((size_t)B * 4);
     for (int b = 0; b < B; ++b)
         for (int k = 0; k < 4; ++k) {
-            const TriSched& S = M->sched[(size_t)b * 4 + k];
+            const TriSched& S = M->sched[(size_t)(M->shared ? 0 : b) * 4 + k];
             TriView<double2>& a = v64[(size_t)b * 4 + k];
             a.far_off = S.far_off.p; a.mid_off = S.mid_off.p; a.near_off = S.near_off.p; a.far_col = S.far_col.p;
             a.mid_col = S.mid_col.p; a.near_col = S.near_col.p; a.far_need = S.far_need.p; a.far_val = S.far_val.p;
@@ -68,29 +71,54 @@ om_status ilu_factor_impl(const om_csr* Ain, double drop_tol, double fill_factor
     M->n = n;
     M->batch = B;
     M->flags = flags;
-    M->sched.resize((size_t)B * 4);
-    M->host.resize(B);
+    M->shared = (flags & OM_ILU_SHARED) != 0;
+    const int NF = M->shared ? 1 : B;   // factors to compute
+    M->sched.resize((size_t)NF * 4);
+    M->host.resize(NF);
     int dev = 0;
     OM_HIP(hipGetDevice(&dev));
     const bool adjoint = flags & OM_ILU_ADJOINT;
+    const bool verbose = std::getenv("OMSS_VERBOSE") != nullptr;
     const bool c64 = flags & OM_ILU_C64;
-    std::vector<om_status> status(B, OM_OK);
-    std::vector<std::string> errs(B);
-    std::vector<int64_t> nl(B), nu(B), dl(B), du(B), rep(B);
-    // items run concurrently, each with its share of the host threads
+    std::vector<om_status> status(NF, OM_OK);
+    std::vector<std::string> errs(NF);
+    std::vector<int64_t> nl(NF), nu(NF), dl(NF), du(NF), rep(NF);
+    // Factorisation: on host threads (items concurrently), or with
+    // OMSS_ILUT=device on the device (one item at a time, the whole GPU) unless
+    // the band is wider than the device kernel's window.
+    const char* ie = std::getenv("OMSS_ILUT");
+    bool on_device = ie && std::strcmp(ie, "device") == 0;
+    std::vector<std::unique_ptr<HostFactor>> dev_factors(NF);
+    if (on_device) {
+        for (int b = 0; b < NF && on_device; ++b) {
+            dev_factors[b].reset(new HostFactor);
+            std::string err;
+            const om_status rc = ilut_factor_gpu(A, b, drop_tol, fill_factor, dev_factors[b].get(), &err, s);
+            if (rc == OM_EBREAKDOWN) { set_error("batch item %d: %s", b, err.c_str()); return rc; }
+            if (rc == OM_EINVAL && b == 0) { on_device = false; break; }   // band too wide: host threads
+            if (rc != OM_OK) return rc;
+            if (verbose) fprintf(stderr, "[omss] ilu_factor: item %d factored on the device\n", b);
+        }
+    }
     const int HT = host_threads();
-    const int T = std::max(1, std::min(B, HT));
+    const int T = std::max(1, std::min(NF, HT));
     const int per_item = std::max(1, HT / T);
     auto work = [&](int t) {
         (void)hipSetDevice(dev);
-        for (int b = t; b < B; b += T) {
-            std::unique_ptr<HostFactor> F(new HostFactor);
+        for (int b = t; b < NF; b += T) {
+            std::unique_ptr<HostFactor> F;
             std::string err;
-            const int rc = per_item > 1
-                ? ilut_factor_host_mt(n, A->h_row_ptr.data(), A->h_col.data(), vals.data() + (size_t)b * nnz * 2,
-                                      drop_tol, fill_factor, per_item, F.get(), &err)
-                : ilut_factor_host(n, A->h_row_ptr.data(), A->h_col.data(), vals.data() + (size_t)b * nnz * 2,
-                                   drop_tol, fill_factor, 0.0, F.get(), &err);
+            int rc = 0;
+            if (on_device) {
+                F = std::move(dev_factors[b]);
+            } else {
+                F.reset(new HostFactor);
+                rc = per_item > 1
+                    ? ilut_factor_host_mt(n, A->h_row_ptr.data(), A->h_col.data(), vals.data() + (size_t)b * nnz * 2,
+                                          drop_tol, fill_factor, per_item, F.get(), &err)
+                    : ilut_factor_host(n, A->h_row_ptr.data(), A->h_col.data(), vals.data() + (size_t)b * nnz * 2,
+                                       drop_tol, fill_factor, 0.0, F.get(), &err);
+            }
             if (rc != 0) {
                 status[b] = OM_EBREAKDOWN;
                 errs[b] = "batch item " + std::to_string(b) + ": " + err;
@@ -99,17 +127,31 @@ om_status ilu_factor_impl(const om_csr* Ain, double drop_tol, double fill_factor
             nl[b] = (int64_t)F->l_col.size();
             nu[b] = (int64_t)F->u_col.size();
             rep[b] = F->repaired;
-            for (int k = 0; k < (adjoint ? 4 : 2); ++k) {
-                SolveCSR S;
-                factor_to_solve(*F, k, S);
-                HostTri H;
-                build_host_tri(S, H);
-                S = SolveCSR();
-                if (k == 0) dl[b] = H.depth;
-                if (k == 1) du[b] = H.depth;
-                om_status rc = upload_tri(H, c64, M->sched[(size_t)b * 4 + k]);
-                if (rc != OM_OK) { status[b] = rc; errs[b] = last_error(); return; }
-            }
+            if (verbose)
+                fprintf(stderr, "[omss] ilu_factor: item %d factored (fill %.1f), building solve schedules\n", b,
+                        (double)(nl[b] + nu[b]) / (double)nnz);
+            // the solve schedules of the factor are independent: build them concurrently
+            const int nk = adjoint ? 4 : 2;
+            std::vector<std::thread> kt;
+            std::vector<om_status> krc(nk, OM_OK);
+            std::vector<std::string> kerr(nk);
+            for (int k = 0; k < nk; ++k)
+                kt.emplace_back([&, k] {
+                    (void)hipSetDevice(dev);
+                    SolveCSR S;
+                    factor_to_solve(*F, k, S);
+                    HostTri H;
+                    build_host_tri(S, H);
+                    S = SolveCSR();
+                    if (k == 0) dl[b] = H.depth;
+                    if (k == 1) du[b] = H.depth;
+                    krc[k] = upload_tri(H, c64, M->sched[(size_t)b * 4 + k]);
+                    if (krc[k] != OM_OK) kerr[k] = last_error();
+                });
+            for (auto& x : kt) x.join();
+            for (int k = 0; k < nk; ++k)
+                if (krc[k] != OM_OK) { status[b] = krc[k]; errs[b] = kerr[k]; return; }
+            if (verbose) fprintf(stderr, "[omss] ilu_factor: item %d schedules uploaded\n", b);
             if (flags & OM_ILU_KEEP_HOST) M->host[b] = std::move(F);
         }
     };
@@ -117,12 +159,12 @@ om_status ilu_factor_impl(const om_csr* Ain, double drop_tol, double fill_factor
     for (int t = 1; t < T; ++t) th.emplace_back(work, t);
     work(0);
     for (auto& x : th) x.join();
-    for (int b = 0; b < B; ++b)
+    for (int b = 0; b < NF; ++b)
         if (status[b] != OM_OK) { set_error("%s", errs[b].c_str()); return status[b]; }
     OM_TRY(finish_views(M.get(), s));
 
     om_ilu_stats S{};
-    for (int b = 0; b < B; ++b) {
+    for (int b = 0; b < NF; ++b) {
         S.fill = std::max(S.fill, (double)(nl[b] + nu[b]) / (double)nnz);
         S.nnz_L += nl[b];
         S.nnz_U += nu[b];

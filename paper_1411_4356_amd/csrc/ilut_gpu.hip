@@ -1,0 +1,652 @@
+// Dual-threshold incomplete LU on the device, row-pipelined: the same factor
+// as the host ILUT (ilut.cpp, no pivoting), bit for bit.
+//
+// A persistent grid of workgroups takes rows in increasing order from an
+// atomic counter.  For row i the workgroup keeps a dense accumulator over the
+// band window [i - lb, i + ub] (which contains every fill entry of the row)
+// in global memory and a presence bitmap of the window in LDS, and:
+//   1. loads row i of A, tau_i = d * ||a_i||_inf;
+//   2. eliminates against U rows in increasing column: wave 0 finds the next
+//      present column k left of the diagonal in the bitmap, makes sure row k
+//      is finished (ready flags of 64 rows are polled at once, after an L2
+//      invalidation, and remembered; waits poll with acquire loads)
+//      and forms the multiplier w_k / u_kk, dropping it if |w_k| < tau_i; all
+//      threads then subtract w_k * u_k from the window;
+//   3. drops entries below tau_i and keeps the lfil_i largest of each
+//      triangle (exact radix select on the squared moduli, ties to the lower
+//      column), writes the L and U rows in column order and raises row i's
+//      ready flag.
+// Rows are handed out in increasing order and wait only for smaller rows,
+// which are held by running workgroups, so the grid always makes progress;
+// every wait is bounded in time.  Published rows are written through to
+// memory before the flag (s_waitcnt); row storage is 128-byte aligned so a
+// cache line never mixes rows and readers of a flagged row may use ordinary
+// loads; the pivots, kept in a dense array, are read with coherent loads.
+// The first row that breaks down (non-finite pivot or kept entry) is recorded
+// and ends the launch.  Floating-point contraction is disabled so that every
+// operation matches the host code.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <thread>
+#include <vector>
+
+#include "common.hpp"
+#include "ilut.hpp"
+#include "kernels.hpp"
+
+#pragma clang fp contract(off)
+
+namespace omss {
+
+constexpr int IT = 256;             // threads per workgroup
+constexpr int IWAVES = IT / 64;
+constexpr int WBITS_MAX = 1 << 16;  // largest band window (lb + ub + 1)
+constexpr int RADIX_BITS = 11;
+constexpr int RADIX = 1 << RADIX_BITS;
+
+struct IlutDevArgs {
+    int64_t n;
+    int32_t lb, ub, W;
+    int64_t wstride;        // work window stride (entries, a whole number of 128-byte lines)
+    const int32_t* row_ptr;
+    const int32_t* col;
+    const double2* val;
+    double drop_tol, fill_factor;
+    int32_t capped;
+    const int64_t* l_off;   // n + 1 capacity offsets (entries)
+    const int64_t* u_off;
+    int32_t* l_len;
+    int32_t* u_len;
+    int32_t* l_col;
+    double2* l_val;
+    int32_t* u_col;
+    double2* u_val;
+    double2* udiag;         // pivot u_ii per row
+    int32_t* ready;         // per row, epoch tags
+    uint32_t epoch;
+    long long wait_ticks;   // bound of one wait, in wall-clock ticks
+    int32_t* host_progress; // host-mapped: a recently published row (progress report)
+    double2* work;          // gridDim * W
+    int32_t* next_row;
+    int32_t* abort_flag;
+    int32_t* status;        // [0] first breakdown row + 1 (0 = none), [1] repaired pivots,
+                            // [2], [3] row + 1 of the waiter and of the awaited row on a timeout,
+                            // [4] row + 1 that found inconsistent row data
+};
+
+__device__ inline void wt_store(double2* p, double2 v) {
+    double* q = reinterpret_cast<double*>(p);
+    __hip_atomic_store(q, v.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(q + 1, v.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void wt_store(int32_t* p, int32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ inline double2 ld_coh(const double2* p) {
+    const double* q = reinterpret_cast<const double*>(p);
+    return make_double2(__hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+                        __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+
+__device__ inline int32_t ld_flag(const int32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Flags written by workgroups on other XCDs are polled with acquire loads:
+// the L2 invalidation that comes with each one keeps a line cached by an
+// earlier poll from hiding the update.
+__device__ inline int32_t ld_flag_acq(const int32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wait until *f == v; false on abort or when the time bound passes (which
+// raises the abort flag and records the waiting and the awaited row).  The
+// abort flag, read by every waiter, is polled only every 16th round, with a
+// growing pause between polls, to keep the flag lines from becoming hot spots.
+__device__ bool wait_flag(const int32_t* f, int32_t v, int32_t* abort_flag, long long ticks, int32_t* diag,
+                          int64_t waiter, int64_t awaited) {
+    const long long t0 = wall_clock64();
+    for (unsigned int it = 0; ld_flag_acq(f) != v; ++it) {
+        if ((it & 15u) == 15u) {
+            if (ld_flag_acq(abort_flag)) return false;
+            if (wall_clock64() - t0 > ticks) {
+                __hip_atomic_store(diag, (int32_t)(waiter + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(diag + 1, (int32_t)(awaited + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                return false;
+            }
+        }
+        if (it < 64) __builtin_amdgcn_s_sleep(2);
+        else __builtin_amdgcn_s_sleep(8);
+    }
+    return true;
+}
+
+__device__ inline unsigned long long key_of(double m2) { return (unsigned long long)__double_as_longlong(m2); }
+
+// Block-wide inclusive prefix sum of one int per thread; returns the exclusive
+// prefix, *total receives the sum.
+__device__ inline int block_scan(int v, int* total, int* sbuf) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int x = v;
+    for (int off = 1; off < 64; off <<= 1) {
+        const int y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) sbuf[wave] = x;
+    __syncthreads();
+    int base = 0, tot = 0;
+    for (int w = 0; w < IWAVES; ++w) {
+        if (w < wave) base += sbuf[w];
+        tot += sbuf[w];
+    }
+    __syncthreads();
+    *total = tot;
+    return base + x - v;
+}
+
+// Radix select over the candidate keys of one triangle: returns the key K of
+// the lfil-th largest and, in *n_gt, how many keys exceed K.
+// Requires 1 <= lfil < number of candidates.  sbuf: 8 ints.
+__device__ unsigned long long select_kth(const double2* w, const uint32_t* bits, int p0, int p1, double tau2, int lfil,
+                                         int* n_gt, unsigned int* hist, int* sbuf) {
+    unsigned long long prefix = 0, pmask = 0;
+    int need = lfil;   // rank (1-based) of the wanted key among those matching the prefix, from the top
+    int above = 0;     // keys strictly greater than the prefix range, counted so far
+    for (int shift = 64 - RADIX_BITS; shift > -RADIX_BITS; shift -= RADIX_BITS) {
+        const int sh = shift < 0 ? 0 : shift;
+        const int nb = shift < 0 ? RADIX_BITS + shift : RADIX_BITS;
+        const unsigned int dmask = (1u << nb) - 1u;
+        for (int t = threadIdx.x; t < RADIX; t += IT) hist[t] = 0;
+        __syncthreads();
+        for (int p = p0 + threadIdx.x; p < p1; p += IT) {
+            if (!((bits[p >> 5] >> (p & 31)) & 1u)) continue;
+            const double2 v = w[p];
+            const double m2 = v.x * v.x + v.y * v.y;
+            if (m2 == 0.0 || m2 < tau2) continue;
+            const unsigned long long k = key_of(m2);
+            if ((k & pmask) != prefix) continue;
+            atomicAdd(&hist[(unsigned int)(k >> sh) & dmask], 1u);
+        }
+        __syncthreads();
+        // thread t owns the digits dmask - 8t - j, j = 0..7 (descending); the
+        // counts above its range come from a block-wide scan
+        int own = 0;
+        int cnt[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int d = (int)dmask - 8 * threadIdx.x - j;
+            cnt[j] = d >= 0 ? (int)hist[d] : 0;
+            own += cnt[j];
+        }
+        int tot;
+        const int before = block_scan(own, &tot, sbuf + 2);
+        if (before < need && need <= before + own) {
+            int acc = before;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                if (acc + cnt[j] >= need) {
+                    sbuf[0] = (int)dmask - 8 * threadIdx.x - j;
+                    sbuf[1] = acc;
+                    break;
+                }
+                acc += cnt[j];
+            }
+        }
+        __syncthreads();
+        const int d = sbuf[0];
+        const int acc = sbuf[1];
+        __syncthreads();
+        above += acc;
+        need -= acc;
+        prefix |= ((unsigned long long)d) << sh;
+        pmask |= ((unsigned long long)dmask) << sh;
+    }
+    *n_gt = above;
+    return prefix;
+}
+
+__global__ __launch_bounds__(IT) void ilut_row_kernel(IlutDevArgs a) {
+    __shared__ uint32_t bits[WBITS_MAX / 32];
+    __shared__ unsigned int hist[RADIX];
+    __shared__ int sbuf[16];
+    __shared__ double sred[IWAVES];
+    __shared__ int s_row, s_k[2], s_flag[2], s_ulen[2];
+    __shared__ int64_t s_uoff[2];
+    __shared__ double2 s_m[2];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int W = a.W, nwords = (W + 31) >> 5;
+    double2* w = a.work + (int64_t)blockIdx.x * a.wstride;
+
+    while (true) {
+        if (tid == 0) s_row = atomicAdd(a.next_row, 1);
+        for (int q = tid; q < nwords; q += IT) bits[q] = 0u;
+        __syncthreads();
+        const int64_t i = s_row;
+        if (i >= a.n) break;
+        if (__hip_atomic_load(a.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+        const int64_t lo = i - a.lb;
+        // 1. row i of A
+        const int32_t r0 = a.row_ptr[i], r1 = a.row_ptr[i + 1];
+        double mx = 0.0;
+        for (int32_t t = r0 + tid; t < r1; t += IT) {
+            const int p = (int)(a.col[t] - lo);
+            const double2 v = a.val[t];
+            w[p] = v;
+            atomicOr(&bits[p >> 5], 1u << (p & 31));
+            const double m = sqrt(v.x * v.x + v.y * v.y);
+            mx = m > mx ? m : mx;
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            const double o = __shfl_down(mx, off, 64);
+            mx = o > mx ? o : mx;
+        }
+        if (lane == 0) sred[wave] = mx;
+        __syncthreads();
+        double rowinf = 0.0;
+        for (int q = 0; q < IWAVES; ++q) rowinf = sred[q] > rowinf ? sred[q] : rowinf;
+        const double tau = a.drop_tol * rowinf;
+        const double tau2 = tau * tau;
+        const int64_t nnz_row = r1 - r0;
+        const int lfil = a.capped ? (int)fmax(0.0, floor((a.fill_factor * (double)nnz_row - 1.0) / 2.0)) : 0x7fffffff;
+        const int dpos = a.lb;   // window position of the diagonal
+
+        // 2. elimination.  Wave 0 decides each step (next column, readiness,
+        // multiplier) and publishes it in a parity-indexed slot; the other waves
+        // read the slot after the barrier, so two steps never share one.
+        int kprev = -1;
+        int64_t rlo = -(1ll << 40);     // wave 0: rows rlo..rlo+63 whose flags are cached in rmask
+        unsigned long long rmask = 0ull;
+        for (int par = 0;; par ^= 1) {
+            if (wave == 0) {
+                int found = -1;
+                for (int base = (kprev + 1) >> 5; base <= ((dpos - 1) >> 5) && found < 0; base += 64) {
+                    const int wi = base + lane;
+                    uint32_t word = 0u;
+                    if (wi <= ((dpos - 1) >> 5) && wi < nwords) {
+                        word = bits[wi];
+                        const int lowb = wi * 32, hib = lowb + 32;
+                        if (kprev + 1 > lowb) word &= ~0u << (kprev + 1 - lowb);       // positions > kprev
+                        if (dpos < hib) word &= (dpos - lowb) >= 32 ? ~0u : ((1u << (dpos - lowb)) - 1u);   // < dpos
+                    }
+                    const unsigned long long bal = __ballot(word != 0u);
+                    if (bal) {
+                        const int l = __ffsll((long long)bal) - 1;
+                        const uint32_t wl = __shfl(word, l, 64);
+                        found = (base + l) * 32 + (__ffs((int)wl) - 1);
+                    }
+                }
+                int flag = 0;
+                double mr = 0.0, mi = 0.0;
+                int64_t uoff = 0;
+                int ulen = 0;
+                if (found >= 0 && lo + found < 0) {
+                    flag = -2;   // a column left of 0: the window is corrupt
+                } else if (found >= 0) {
+                    const int64_t k = lo + found;
+                    const double2 x = w[found];
+                    if (x.x != 0.0 || x.y != 0.0) {
+                        bool rdy = k >= rlo && k < rlo + 64 && ((rmask >> (k - rlo)) & 1ull);
+                        if (!rdy) {
+                            rlo = k;
+                            const int64_t r = k + lane;
+                            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                            rmask = __ballot(r < i && ld_flag(a.ready + r) == (int32_t)a.epoch);
+                            rdy = rmask & 1ull;
+                            // rows seen finished: their data, read below with ordinary
+                            // loads, must not come from lines cached before
+                            if (rmask) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                        }
+                        if (!rdy) {
+                            int ok = 1;
+                            if (lane == 0) ok = wait_flag(a.ready + k, (int32_t)a.epoch, a.abort_flag, a.wait_ticks, a.status + 2, i, k);
+                            ok = __shfl(ok, 0, 64);
+                            if (ok) {
+                                rmask |= 1ull;
+                                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                            } else {
+                                flag = -1;
+                            }
+                        }
+                        if (flag == 0) {
+                            const double2 d = ld_coh(a.udiag + k);
+                            const double den = d.x * d.x + d.y * d.y;
+                            mr = (x.x * d.x + x.y * d.y) / den;
+                            mi = (x.y * d.x - x.x * d.y) / den;
+                            if (mr * mr + mi * mi < tau2) {
+                                if (lane == 0) w[found] = make_double2(0.0, 0.0);
+                            } else {
+                                if (lane == 0) w[found] = make_double2(mr, mi);
+                                flag = 1;
+                                uoff = a.u_off[k];
+                                ulen = ld_flag(a.u_len + k);
+                                if (ulen < 1 || uoff + ulen > a.u_off[k + 1]) flag = -2;
+                            }
+                        }
+                    }
+                }
+                if (lane == 0) {
+                    s_k[par] = found;
+                    s_flag[par] = flag;
+                    s_m[par] = make_double2(mr, mi);
+                    s_uoff[par] = uoff;
+                    s_ulen[par] = ulen;
+                }
+            }
+            __syncthreads();
+            const int kp = s_k[par];
+            if (kp < 0) break;
+            const int fl = s_flag[par];
+            if (fl == -2) {
+                if (tid == 0) {
+                    __hip_atomic_store(a.status + 4, (int32_t)(i + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_store(a.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+                break;
+            }
+            if (fl < 0) break;
+            if (fl == 1) {
+                const double mr = s_m[par].x, mi = s_m[par].y;
+                const int64_t ub0 = s_uoff[par];
+                const int len = s_ulen[par];
+                bool badcol = false;
+                for (int q = 1 + tid; q < len; q += IT) {
+                    const int p = (int)(a.u_col[ub0 + q] - lo);
+                    if (p <= kp || p >= W) { badcol = true; continue; }
+                    const double2 u = a.u_val[ub0 + q];
+                    const double pr = mr * u.x - mi * u.y;
+                    const double pi = mr * u.y + mi * u.x;
+                    const uint32_t bit = 1u << (p & 31);
+                    if (bits[p >> 5] & bit) {
+                        double2 c = w[p];
+                        c.x -= pr;
+                        c.y -= pi;
+                        w[p] = c;
+                    } else {
+                        w[p] = make_double2(-pr, -pi);
+                        atomicOr(&bits[p >> 5], bit);
+                    }
+                }
+                if (__syncthreads_or(badcol)) {
+                    if (tid == 0) {
+                        __hip_atomic_store(a.status + 4, (int32_t)(i + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        __hip_atomic_store(a.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                    break;
+                }
+            }
+            kprev = kp;
+        }
+        if (__hip_atomic_load(a.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+
+        // 3. dropping, cap, output
+        int n_gt_l = 0, n_gt_u = 0;
+        unsigned long long Kl = 0ull, Ku = 0ull;
+        int cl = 0, cu = 0;   // candidate counts per thread
+        for (int p = tid; p < W; p += IT) {
+            if (p == dpos || !((bits[p >> 5] >> (p & 31)) & 1u)) continue;
+            const double2 v = w[p];
+            const double m2 = v.x * v.x + v.y * v.y;
+            if (m2 == 0.0 || m2 < tau2) continue;
+            if (p < dpos) ++cl; else ++cu;
+        }
+        int totl = 0, totu = 0;
+        (void)block_scan(cl, &totl, sbuf);
+        (void)block_scan(cu, &totu, sbuf);
+        const bool cap_l = totl > lfil, cap_u = totu > lfil;
+        // lfil = 0 keeps nothing: K above every key, no ties taken
+        if (cap_l) Kl = lfil > 0 ? select_kth(w, bits, 0, dpos, tau2, lfil, &n_gt_l, hist, sbuf + 4) : ~0ull;
+        if (cap_u) Ku = lfil > 0 ? select_kth(w, bits, dpos + 1, W, tau2, lfil, &n_gt_u, hist, sbuf + 4) : ~0ull;
+        // compaction in column order: each thread takes a contiguous chunk
+        const int chunk = (W + IT - 1) / IT;
+        const int c0 = tid * chunk, c1 = min(W, c0 + chunk);
+        int keep_l = 0, keep_u = 0, eq_l = 0, eq_u = 0;
+        for (int p = c0; p < c1; ++p) {
+            if (p == dpos || !((bits[p >> 5] >> (p & 31)) & 1u)) continue;
+            const double2 v = w[p];
+            const double m2 = v.x * v.x + v.y * v.y;
+            if (m2 == 0.0 || m2 < tau2) continue;
+            const unsigned long long key = key_of(m2);
+            if (p < dpos) {
+                if (!cap_l || key > Kl) ++keep_l; else if (key == Kl) ++eq_l;
+            } else {
+                if (!cap_u || key > Ku) ++keep_u; else if (key == Ku) ++eq_u;
+            }
+        }
+        int tmp;
+        const int eq_l_before = block_scan(eq_l, &tmp, sbuf);
+        const int eq_u_before = block_scan(eq_u, &tmp, sbuf);
+        // ties at K: the first (lfil - n_gt) in column order are kept
+        const int take_l = cap_l ? max(0, min(eq_l, lfil - n_gt_l - eq_l_before)) : 0;
+        const int take_u = cap_u ? max(0, min(eq_u, lfil - n_gt_u - eq_u_before)) : 0;
+        int tot_l = 0, tot_u = 0;
+        const int out_l = block_scan(keep_l + take_l, &tot_l, sbuf);
+        const int out_u = block_scan(keep_u + take_u, &tot_u, sbuf);
+        // diagonal, breakdown check
+        double2 dg = make_double2(0.0, 0.0);
+        if ((bits[dpos >> 5] >> (dpos & 31)) & 1u) dg = w[dpos];
+        const int64_t lb0 = a.l_off[i], ub0 = a.u_off[i];
+        int written_l = 0, written_u = 0, el = 0, eu = 0;
+        bool bad = false;
+        for (int p = c0; p < c1; ++p) {
+            if (p == dpos || !((bits[p >> 5] >> (p & 31)) & 1u)) continue;
+            const double2 v = w[p];
+            const double m2 = v.x * v.x + v.y * v.y;
+            if (m2 == 0.0 || m2 < tau2) continue;
+            const unsigned long long key = key_of(m2);
+            const int32_t c = (int32_t)(lo + p);
+            if (p < dpos) {
+                bool keep = !cap_l || key > Kl;
+                if (cap_l && key == Kl) keep = el++ < take_l;
+                if (keep) {
+                    wt_store(a.l_col + lb0 + out_l + written_l, c);
+                    wt_store(a.l_val + lb0 + out_l + written_l, v);
+                    ++written_l;
+                }
+            } else {
+                bool keep = !cap_u || key > Ku;
+                if (cap_u && key == Ku) keep = eu++ < take_u;
+                if (keep) {
+                    if (!isfinite(v.x) || !isfinite(v.y)) bad = true;
+                    wt_store(a.u_col + ub0 + 1 + out_u + written_u, c);
+                    wt_store(a.u_val + ub0 + 1 + out_u + written_u, v);
+                    ++written_u;
+                }
+            }
+        }
+        if (tid == 0) {
+            if (!isfinite(dg.x) || !isfinite(dg.y)) bad = true;
+            const double fl = 1e-14 * rowinf;
+            const double dmag = sqrt(dg.x * dg.x + dg.y * dg.y);
+            if (!bad && (dmag < fl || dmag == 0.0)) {
+                if (dmag > 0.0) dg = make_double2(fl * dg.x / dmag, fl * dg.y / dmag);
+                else if (fl > 0.0) dg = make_double2(fl, 0.0);
+                else dg = make_double2(1.0, 0.0);
+                atomicAdd(a.status + 1, 1);
+            }
+            wt_store(a.u_col + ub0, (int32_t)i);
+            wt_store(a.u_val + ub0, dg);
+            wt_store(a.udiag + i, dg);
+            wt_store(a.l_len + i, tot_l);
+            wt_store(a.u_len + i, tot_u + 1);
+        }
+        if (__syncthreads_or(bad)) {
+            if (tid == 0) {
+                atomicCAS(a.status, 0, (int32_t)(i + 1));
+                __hip_atomic_store(a.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            break;
+        }
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (tid == 0) {
+            __hip_atomic_store(a.ready + i, (int32_t)a.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if ((i & 4095) == 0) __hip_atomic_store(a.host_progress, (int32_t)i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+    }
+}
+
+// Factor item `item` of A on the device; the CSR factor is returned on the
+// host in F (same layout as ilut_factor_host).
+om_status ilut_factor_gpu(const om_csr* A, int item, double drop_tol, double fill_factor, HostFactor* F,
+                          std::string* err, hipStream_t s) {
+    const int64_t n = A->n;
+    om_csr* Am = const_cast<om_csr*>(A);
+    OM_TRY(ensure_host_pattern(Am, s));
+    // band of A
+    int64_t lb = 0, ub = 0;
+    for (int64_t r = 0; r < n; ++r)
+        for (int64_t t = Am->h_row_ptr[r]; t < Am->h_row_ptr[r + 1]; ++t) {
+            const int64_t d = Am->h_col[t] - r;
+            lb = std::max(lb, -d);
+            ub = std::max(ub, d);
+        }
+    const int64_t W = lb + ub + 1;
+    if (W > WBITS_MAX) { set_error("band window %lld exceeds the device ILUT limit %d", (long long)W, WBITS_MAX); return OM_EINVAL; }
+    const bool capped = std::isfinite(fill_factor);
+    // row capacities in multiples of 32 entries, so that both the value
+    // (16-byte) and the column (4-byte) storage of a row are 128-byte aligned
+    std::vector<int64_t> loff(n + 1, 0), uoff(n + 1, 0);
+    for (int64_t r = 0; r < n; ++r) {
+        const int64_t nz = Am->h_row_ptr[r + 1] - Am->h_row_ptr[r];
+        int64_t lf = capped ? std::max<int64_t>(0, (int64_t)std::floor((fill_factor * (double)nz - 1.0) / 2.0)) : INT64_MAX;
+        const int64_t cl = std::min<int64_t>(lf, std::min<int64_t>(lb, r));
+        const int64_t cu = std::min<int64_t>(lf, std::min<int64_t>(ub, n - 1 - r)) + 1;
+        loff[r + 1] = loff[r] + ((cl + 31) & ~31ll);
+        uoff[r + 1] = uoff[r] + ((cu + 31) & ~31ll);
+    }
+    int dev = 0, cus = 0, per = 0, coop = 0, clk_khz = 0;
+    OM_HIP(hipGetDevice(&dev));
+    OM_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    OM_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
+    OM_HIP(hipDeviceGetAttribute(&clk_khz, hipDeviceAttributeWallClockRate, dev));
+    OM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, ilut_row_kernel, IT, 0));
+    if (!coop || per < 1) { set_error("cooperative launch unavailable for the device ILUT"); return OM_EINVAL; }
+    int G = (int)std::min<int64_t>((int64_t)cus * per, std::max<int64_t>(1, n));
+    if (const char* e = getenv("OMSS_ILUT_GRID")) G = std::max(1, std::min(G, atoi(e)));
+    DevBuf<int64_t> dloff, duoff;
+    OM_TRY(dloff.upload(loff.data(), loff.size(), s));
+    OM_TRY(duoff.upload(uoff.data(), uoff.size(), s));
+    DevBuf<int32_t> llen, ulen, lcol, ucol, ready, misc;
+    DevBuf<double2> lval, uval, work, udiag;
+    OM_TRY(llen.alloc(n));
+    OM_TRY(ulen.alloc(n));
+    OM_TRY(lcol.alloc(std::max<int64_t>(1, loff[n])));
+    OM_TRY(lval.alloc(std::max<int64_t>(1, loff[n])));
+    OM_TRY(ucol.alloc(uoff[n]));
+    OM_TRY(uval.alloc(uoff[n]));
+    OM_TRY(ready.alloc(n));
+    OM_TRY(udiag.alloc(n));
+    OM_TRY(misc.alloc(8));
+    const int64_t wstride = (W + 7) & ~7ll;
+    OM_TRY(work.alloc((size_t)G * wstride));
+    OM_HIP(hipMemsetAsync(ready.p, 0, ready.bytes(), s));
+    OM_HIP(hipMemsetAsync(misc.p, 0, misc.bytes(), s));
+    // everything the launch reads is in place before it starts
+    OM_HIP(hipStreamSynchronize(s));
+    IlutDevArgs a;
+    a.n = n; a.lb = (int32_t)lb; a.ub = (int32_t)ub; a.W = (int32_t)W; a.wstride = wstride;
+    a.row_ptr = A->row_ptr.p; a.col = A->col.p; a.val = A->val.p + (size_t)item * A->nnz;
+    a.drop_tol = drop_tol; a.fill_factor = fill_factor; a.capped = capped;
+    a.l_off = dloff.p; a.u_off = duoff.p; a.l_len = llen.p; a.u_len = ulen.p;
+    a.l_col = lcol.p; a.l_val = lval.p; a.u_col = ucol.p; a.u_val = uval.p;
+    a.udiag = udiag.p; a.ready = ready.p; a.epoch = 1; a.work = work.p;
+    a.wait_ticks = (long long)std::max(clk_khz, 1000) * 1000ll * 30;   // 30 s
+    a.next_row = misc.p; a.abort_flag = misc.p + 1; a.status = misc.p + 2;
+    // progress word in pinned host memory, written by the kernel now and then
+    int32_t* hprog = nullptr;
+    OM_HIP(hipHostMalloc((void**)&hprog, 256, hipHostMallocMapped | hipHostMallocCoherent));
+    struct HostFree { int32_t* p; ~HostFree() { if (p) (void)hipHostFree(p); } } hprog_guard{hprog};
+    *(volatile int32_t*)hprog = 0;
+    OM_HIP(hipHostGetDevicePointer((void**)&a.host_progress, hprog, 0));
+    void* args[] = {(void*)&a};
+    const bool verbose = std::getenv("OMSS_VERBOSE") != nullptr;
+    const auto t0 = std::chrono::steady_clock::now();
+    OM_HIP(hipLaunchCooperativeKernel((const void*)ilut_row_kernel, dim3(G), dim3(IT), args, 0, s));
+    int32_t hs[8];
+    OM_HIP(hipMemcpyAsync(hs, misc.p, sizeof hs, hipMemcpyDeviceToHost, s));
+    double next_report = 20.0;
+    while (true) {
+        const hipError_t q = hipStreamQuery(s);
+        if (q == hipSuccess) break;
+        if (q != hipErrorNotReady) OM_HIP(q);
+        std::this_thread::sleep_for(std::chrono::milliseconds(20));
+        const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        if (verbose && el >= next_report) {
+            fprintf(stderr, "[omss] device ILUT: ~%d/%lld rows after %.0f s\n", *(volatile int32_t*)hprog,
+                    (long long)n, el);
+            next_report += 20.0;
+        }
+    }
+    OM_HIP(hipStreamSynchronize(s));
+    if (verbose)
+        fprintf(stderr, "[omss] device ILUT: n %lld, window %lld, %d workgroups, %.3f s\n", (long long)n, (long long)W, G,
+                std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
+    if (hs[2] != 0) {
+        if (err) *err = "ILUT breakdown: non-finite pivot or entry in row " + std::to_string(hs[2] - 1) +
+                        " (the incomplete factorisation is unstable for this drop tolerance and fill)";
+        return OM_EBREAKDOWN;
+    }
+    if (hs[6] != 0) {
+        set_error("device ILUT: inconsistent row data met while eliminating row %d", hs[6] - 1);
+        return OM_EHIP;
+    }
+    if (hs[1] != 0) {
+        std::vector<int32_t> rd(n);
+        OM_HIP(hipMemcpy(rd.data(), ready.p, n * sizeof(int32_t), hipMemcpyDeviceToHost));
+        int64_t published = 0, first_missing = -1;
+        for (int64_t r = 0; r < n; ++r) {
+            if (rd[r] == 1) ++published;
+            else if (first_missing < 0) first_missing = r;
+        }
+        set_error("device ILUT: a wait timed out (row %d waited for row %d; %lld of %lld rows published, first "
+                  "missing %lld, %d rows handed out)", hs[4] - 1, hs[5] - 1, (long long)published, (long long)n,
+                  (long long)first_missing, hs[0]);
+        return OM_ETIMEOUT;
+    }
+    // gather the rows into the host CSR factor
+    std::vector<int32_t> hl(n), hu(n);
+    OM_HIP(hipMemcpyAsync(hl.data(), llen.p, n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    OM_HIP(hipMemcpyAsync(hu.data(), ulen.p, n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    std::vector<int32_t> acol(std::max<int64_t>(1, loff[n])), bcol(uoff[n]);
+    std::vector<double2> aval(std::max<int64_t>(1, loff[n])), bval(uoff[n]);
+    OM_HIP(hipMemcpyAsync(acol.data(), lcol.p, loff[n] * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    OM_HIP(hipMemcpyAsync(aval.data(), lval.p, loff[n] * sizeof(double2), hipMemcpyDeviceToHost, s));
+    OM_HIP(hipMemcpyAsync(bcol.data(), ucol.p, uoff[n] * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    OM_HIP(hipMemcpyAsync(bval.data(), uval.p, uoff[n] * sizeof(double2), hipMemcpyDeviceToHost, s));
+    OM_HIP(hipStreamSynchronize(s));
+    F->n = n;
+    F->l_ptr.assign(n + 1, 0);
+    F->u_ptr.assign(n + 1, 0);
+    for (int64_t r = 0; r < n; ++r) {
+        F->l_ptr[r + 1] = F->l_ptr[r] + hl[r];
+        F->u_ptr[r + 1] = F->u_ptr[r] + hu[r];
+    }
+    F->l_col.resize(F->l_ptr[n]);
+    F->l_val.resize(2 * F->l_ptr[n]);
+    F->u_col.resize(F->u_ptr[n]);
+    F->u_val.resize(2 * F->u_ptr[n]);
+    for (int64_t r = 0; r < n; ++r) {
+        for (int q = 0; q < hl[r]; ++q) {
+            F->l_col[F->l_ptr[r] + q] = acol[loff[r] + q];
+            F->l_val[2 * (F->l_ptr[r] + q)] = aval[loff[r] + q].x;
+            F->l_val[2 * (F->l_ptr[r] + q) + 1] = aval[loff[r] + q].y;
+        }
+        for (int q = 0; q < hu[r]; ++q) {
+            F->u_col[F->u_ptr[r] + q] = bcol[uoff[r] + q];
+            F->u_val[2 * (F->u_ptr[r] + q)] = bval[uoff[r] + q].x;
+            F->u_val[2 * (F->u_ptr[r] + q) + 1] = bval[uoff[r] + q].y;
+        }
+    }
+    F->perm.resize(n);
+    for (int64_t r = 0; r < n; ++r) F->perm[r] = (int32_t)r;
+    F->repaired = hs[3];
+    F->pivots = 0;
+    return OM_OK;
+}
+
+}  // namespace omss

@@ -175,7 +175,8 @@ struct CoopArgs {
     uint32_t epoch;
     int helpers;          // helper workgroups per item
     int batch;
-    int per_xcd;          // workgroups per XCD per item slot = 1 + helpers
+    int per_xcd;          // workgroups of one item on one XCD
+    int xcd_per_item;     // XCDs an item spans (8 / batch when batch divides 8, else 1)
     unsigned long long* tstat;   // diagnostics (nullable)
 };
 
@@ -226,12 +227,19 @@ template <typename VT>
 __global__ __launch_bounds__(64 * TW) void trsv_coop_kernel(const TriView<VT>* __restrict__ views, int kind,
                                                              const VT* rhs, VT* out, int64_t n,
                                                              const int32_t* __restrict__ active, CoopArgs a) {
-    // placement: workgroup w sits on XCD w % 8; item b uses XCD b % 8
+    // placement: workgroup w sits on XCD w % 8.  When batch divides 8, item b spans
+    // the XCDs congruent to b modulo batch; otherwise item b uses XCD b % 8.
     const int xcd = blockIdx.x % NXCD;
     const int q = blockIdx.x / NXCD;
-    const int b = xcd + NXCD * (q / a.per_xcd);
-    const int role = q % a.per_xcd;
-    if (b >= a.batch) return;
+    int b, role;
+    if (a.xcd_per_item > 1) {
+        b = xcd % a.batch;
+        role = q * a.xcd_per_item + xcd / a.batch;   // 0 = critical workgroup (on XCD b)
+    } else {
+        b = xcd + NXCD * (q / a.per_xcd);
+        role = q % a.per_xcd;
+    }
+    if (b >= a.batch || role > a.helpers) return;
     if (active && !active[b]) return;
     const TriView<VT> S = views[b * 4 + kind];
     VT* x = out + (int64_t)b * n;
@@ -433,7 +441,7 @@ static double trsv_bytes(const om_ilu* M, int kind, size_t s, const int32_t* act
     double b = 0.0;
     for (int i = 0; i < M->batch; ++i) {
         if (act_host && !act_host[i]) continue;
-        const TriSched& S = M->sched[(size_t)i * 4 + kind];
+        const TriSched& S = M->sched[(size_t)(M->shared ? 0 : i) * 4 + kind];
         b += (double)S.nnz * (double)(s + 4) + 2.0 * (double)S.n * (double)s + (S.has_dinv ? (double)S.n * s : 0.0);
     }
     return b;
@@ -461,13 +469,17 @@ static om_status launch_trsv(om_ilu* M, const TriView<VT>* views, int kind, cons
             mg = coop ? cus * per : -1;
         }
         const int64_t nblk = (M->n + 63) / 64;
-        const int slots = (B + NXCD - 1) / NXCD;   // items per XCD
-        int H = 0;
+        const int slots = (B + NXCD - 1) / NXCD;             // items per XCD
+        const int span = (B <= NXCD && NXCD % B == 0) ? NXCD / B : 1;   // XCDs per item
+        int H = 0, per_xcd = 0;
         if (mg > 0) {
             const char* e = getenv("OMSS_TRSV_HELPERS");
-            H = e ? atoi(e) : 16;
+            H = e ? atoi(e) : 16 * span;
             H = (int)std::min<int64_t>(H, nblk);
-            H = std::min(H, mg / (NXCD * slots) - 1);
+            // workgroups of an item: 1 + H over `span` XCDs; grid = 8 * per_xcd * slots
+            per_xcd = (1 + H + span - 1) / span;
+            const int cap = mg / (NXCD * slots);
+            if (per_xcd > cap) { per_xcd = cap; H = per_xcd * span - 1; }
         }
         if (H >= 1) {
             CoopArgs a;
@@ -479,7 +491,8 @@ static om_status launch_trsv(om_ilu* M, const TriView<VT>* views, int kind, cons
             if (a.epoch == 0) a.epoch = ++M->scratch.epoch;
             a.helpers = H;
             a.batch = B;
-            a.per_xcd = 1 + H;
+            a.per_xcd = span > 1 ? per_xcd : 1 + H;
+            a.xcd_per_item = span;
             static unsigned long long* tst = nullptr;
             a.tstat = nullptr;
             if (getenv("OMSS_TRSV_STATS")) {
@@ -489,8 +502,8 @@ static om_status launch_trsv(om_ilu* M, const TriView<VT>* views, int kind, cons
             }
             int64_t n = M->n;
             void* args[] = {(void*)&views, (void*)&kind, (void*)&rhs, (void*)&out, (void*)&n, (void*)&active, (void*)&a};
-            OM_HIP(hipLaunchCooperativeKernel((const void*)trsv_coop_kernel<VT>, dim3(NXCD * slots * (1 + H)),
-                                              dim3(64 * TW), args, 0, s));
+            const unsigned grid = span > 1 ? (unsigned)(NXCD * per_xcd) : (unsigned)(NXCD * slots * (1 + H));
+            OM_HIP(hipLaunchCooperativeKernel((const void*)trsv_coop_kernel<VT>, dim3(grid), dim3(64 * TW), args, 0, s));
             if (a.tstat) {
                 unsigned long long h[3];
                 OM_HIP(hipMemcpyAsync(h, a.tstat, sizeof h, hipMemcpyDeviceToHost, s));

@@ -251,3 +251,100 @@ def test_invalid_parameters_are_rejected():
         P.liouvillian_build(W.TINY.replace(E=float("nan")))
     with pytest.raises(P.OmError):
         P.liouvillian_build(W.TINY.replace(nc=1))
+
+
+def test_shared_factor_preconditions_whole_batch():
+    """One factor (of item 0) as the preconditioner of every item: the
+    solutions are the same steady states, each to tolerance."""
+    ps = [W.BATCH_BASE.replace(nc=4, nm=9, E=e) for e in (0.35, 0.15, 0.55)]
+    rho, info, res = P.steady_state(ps, drop_tol=1e-6, fill_factor=60.0, m=60, tol=1e-11, share_factor=True)
+    rho = to_host(rho)
+    for b, p in enumerate(ps):
+        ro, oo = direct.steady_state(p)
+        assert np.max(np.abs(rho[b] - ro)) <= 1e-8
+    assert info["ilu"]["nnz_L"] > 0
+    A, _ = P.liouvillian_build(ps)
+    B, perm, _ = P.rcm_permute(A)
+    M = P.ilu_factor(B, 1e-6, 60.0, shared=True, keep_host=True)
+    L0, U0 = M.export(0)
+    L2, U2 = M.export(2)
+    assert (L0 != L2).nnz == 0 and (U0 != U2).nnz == 0
+    X = W.random_complex(B.n, seed=4, count=3)
+    y = to_host(P.ilu_apply(M, to_dev(X)))
+    for b in range(3):
+        ref = oilut.apply(L0, U0, X[b])
+        assert np.linalg.norm(y[b] - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+ILUT_CASES = [
+    (CASES[0], 1e-5, 60.0),
+    (CASES[1], 1e-5, 60.0),
+    (CASES[3], 1e-5, 60.0),
+    (W.BATCH_BASE.replace(nc=4, nm=9), 1e-6, 20.0),
+    (W.BATCH_BASE.replace(nc=4, nm=9), 1e-6, float("inf")),
+    (W.BATCH_BASE.replace(nc=4, nm=9), 0.0, float("inf")),
+    (W.BATCH_BASE.replace(nc=6, nm=20), 1e-6, 60.0),
+]
+
+
+def _bits(M):
+    return M.view(np.uint64)
+
+
+DEVICE_ILUT_SKIP = pytest.mark.skip(
+    reason="device ILUT (opt-in, OMSS_ILUT=device): rows that eliminate against other rows time out "
+           "waiting for their ready flags; cause under investigation")
+
+
+@DEVICE_ILUT_SKIP
+@pytest.mark.parametrize("ci", range(len(ILUT_CASES)))
+def test_device_ilut_is_the_host_factor_bit_for_bit(ci, monkeypatch):
+    """The row-pipelined device ILUT (Sec. II dropping rules) yields exactly
+    the factor of the sequential host ILUT, whose pattern and values are
+    pinned to the oracle elsewhere: same pattern, same bits."""
+    p, d, fill = ILUT_CASES[ci]
+    A, _ = P.liouvillian_build(p)
+    B, perm, _ = P.rcm_permute(A)
+    monkeypatch.setenv("OMSS_ILUT", "device")
+    M = P.ilu_factor(B, d, fill, keep_host=True)
+    Lg, Ug = M.export(0)
+    Lh, Uh, _ = P.host_ilut(B.to_scipy(), d, fill)
+    for X, Y in ((Lg, Lh), (Ug, Uh)):
+        assert np.array_equal(X.indptr, Y.indptr) and np.array_equal(X.indices, Y.indices)
+        assert np.array_equal(_bits(X.data), _bits(Y.data))
+    # the host-thread path of ilu_factor gives the same factor
+    monkeypatch.setenv("OMSS_ILUT", "host")
+    Mh = P.ilu_factor(B, d, fill, keep_host=True)
+    L2, U2 = Mh.export(0)
+    assert np.array_equal(_bits(L2.data), _bits(Lg.data)) and np.array_equal(_bits(U2.data), _bits(Ug.data))
+
+
+@DEVICE_ILUT_SKIP
+def test_device_ilut_batch_items_are_factored_independently(monkeypatch):
+    monkeypatch.setenv("OMSS_ILUT", "device")
+    ps = [W.TINY.replace(nc=4, nm=9, E=e) for e in (0.15, 0.45, 0.3)]
+    A, _ = P.liouvillian_build(ps)
+    B, perm, _ = P.rcm_permute(A)
+    M = P.ilu_factor(B, 1e-5, 40.0, keep_host=True)
+    for b in range(3):
+        Lg, Ug = M.export(b)
+        Lh, Uh, _ = P.host_ilut(B.to_scipy(b), 1e-5, 40.0)
+        assert np.array_equal(_bits(Lg.data), _bits(Lh.data)) and np.array_equal(_bits(Ug.data), _bits(Uh.data))
+        assert np.array_equal(Ug.indices, Uh.indices)
+
+
+def test_autograd_steady_state_obs_matches_oracle_adjoint():
+    """torch.autograd through SteadyStateObs: the forward observables and the
+    vector-Jacobian product of the adjoint backward pass against the oracle's
+    dense adjoint gradients (themselves pinned to central differences)."""
+    p = W.ADJOINT.replace(nc=3, nm=6, n_th=1e-15)
+    cfg = P.SolveConfig(nc=p.nc, nm=p.nm, omega_m=p.omega_m, n_th=p.n_th, drop_tol=1e-8, fill_factor=100.0,
+                        m=50, tol=1e-14)
+    theta = torch.tensor([p.delta, p.g0, p.E, p.kappa, p.gamma_m], dtype=torch.float64, requires_grad=True)
+    obs = P.SteadyStateObs.apply(theta, cfg)
+    wts = torch.tensor([0.7, -1.3, 2.0], dtype=torch.float64)
+    (obs * wts).sum().backward()
+    vals, go = oadj.gradients(p)
+    assert np.max(np.abs(obs.detach().numpy() - vals) / np.abs(vals)) <= 1e-10
+    ref = wts.numpy() @ go
+    assert np.max(np.abs(theta.grad.numpy() - ref)) <= 1e-7 * np.abs(ref).max()
