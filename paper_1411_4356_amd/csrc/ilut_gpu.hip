@@ -45,6 +45,7 @@ constexpr int IT = 256;             // threads per workgroup
 constexpr int IWAVES = IT / 64;
 constexpr int WBITS_MAX = 1 << 16;  // largest band window (lb + ub + 1)
 constexpr int RADIX_BITS = 11;
+constexpr int FLAG_STRIDE = 32;     // one 128-byte line per row's ready flag
 constexpr int RADIX = 1 << RADIX_BITS;
 
 struct IlutDevArgs {
@@ -96,32 +97,37 @@ __device__ inline int32_t ld_flag(const int32_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Flags written by workgroups on other XCDs are polled with acquire loads:
-// the L2 invalidation that comes with each one keeps a line cached by an
-// earlier poll from hiding the update.
-__device__ inline int32_t ld_flag_acq(const int32_t* p) {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+// Flags that cross workgroups.  Each row's flag has a cache line of its own,
+// so that waiters on different rows poll different lines and no flag shares
+// a line with another row's; waits back off exponentially and look at the
+// abort flag rarely: hundreds of waves polling a few lines without pause
+// saturate the memory channel behind them and stall every access routed
+// there, including the stores of the rows being waited for.
+__device__ inline void publish_flag(int32_t* p, int32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Wait until *f == v; false on abort or when the time bound passes (which
 // raises the abort flag and records the waiting and the awaited row).  The
 // abort flag, read by every waiter, is polled only every 16th round, with a
 // growing pause between polls, to keep the flag lines from becoming hot spots.
-__device__ bool wait_flag(const int32_t* f, int32_t v, int32_t* abort_flag, long long ticks, int32_t* diag,
+__device__ bool wait_flag(int32_t* f, int32_t v, int32_t* abort_flag, long long ticks, int32_t* diag,
                           int64_t waiter, int64_t awaited) {
     const long long t0 = wall_clock64();
-    for (unsigned int it = 0; ld_flag_acq(f) != v; ++it) {
-        if ((it & 15u) == 15u) {
-            if (ld_flag_acq(abort_flag)) return false;
+    unsigned int pause = 1;
+    for (unsigned int it = 0; ld_flag(f) != v; ++it) {
+        if ((it & 63u) == 63u) {
+            if (ld_flag(abort_flag)) return false;
             if (wall_clock64() - t0 > ticks) {
-                __hip_atomic_store(diag, (int32_t)(waiter + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                __hip_atomic_store(diag + 1, (int32_t)(awaited + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (atomicCAS(diag, 0, (int32_t)(waiter + 1)) == 0)
+                    __hip_atomic_store(diag + 1, (int32_t)(awaited + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                publish_flag(abort_flag, 1);
                 return false;
             }
         }
-        if (it < 64) __builtin_amdgcn_s_sleep(2);
-        else __builtin_amdgcn_s_sleep(8);
+        // exponential back-off, 64 to 8192 cycles
+        for (unsigned int q = 0; q < pause; ++q) __builtin_amdgcn_s_sleep(1);
+        if (pause < 128) pause <<= 1;
     }
     return true;
 }
@@ -145,8 +151,19 @@ __device__ inline int block_scan(int v, int* total, int* sbuf) {
         tot += sbuf[w];
     }
     __syncthreads();
-    *total = tot;
+    *total = __builtin_amdgcn_readfirstlane(tot);
     return base + x - v;
+}
+
+// Block-wide OR of one predicate per thread; the result is wave-uniform.
+__device__ inline int block_or(bool v, int* sor) {
+    const unsigned long long b = __ballot(v);
+    if ((threadIdx.x & 63) == 0) sor[threadIdx.x >> 6] = b != 0ull;
+    __syncthreads();
+    int r = 0;
+    for (int w = 0; w < IWAVES; ++w) r |= sor[w];
+    __syncthreads();
+    return __builtin_amdgcn_readfirstlane(r);
 }
 
 // Radix select over the candidate keys of one triangle: returns the key K of
@@ -198,8 +215,8 @@ __device__ unsigned long long select_kth(const double2* w, const uint32_t* bits,
             }
         }
         __syncthreads();
-        const int d = sbuf[0];
-        const int acc = sbuf[1];
+        const int d = __builtin_amdgcn_readfirstlane(sbuf[0]);
+        const int acc = __builtin_amdgcn_readfirstlane(sbuf[1]);
         __syncthreads();
         above += acc;
         need -= acc;
@@ -215,20 +232,32 @@ __global__ __launch_bounds__(IT) void ilut_row_kernel(IlutDevArgs a) {
     __shared__ unsigned int hist[RADIX];
     __shared__ int sbuf[16];
     __shared__ double sred[IWAVES];
-    __shared__ int s_row, s_k[2], s_flag[2], s_ulen[2];
+    __shared__ int s_row, s_stop, s_or[IWAVES];
+    __shared__ int s_k[2], s_flag[2], s_ulen[2];
     __shared__ int64_t s_uoff[2];
     __shared__ double2 s_m[2];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // Every loop below is controlled by wave-uniform values (read with
+    // readfirstlane from shared memory) and has no early exit; per-lane work
+    // (lane 0 fetching the next row, publishing a row) sits between two
+    // barriers, never at a loop head or latch.  Otherwise the compiler may let
+    // the lanes of one wave take different trips through a loop that contains
+    // barriers, and the waves of a block drift apart.
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int W = a.W, nwords = (W + 31) >> 5;
     double2* w = a.work + (int64_t)blockIdx.x * a.wstride;
 
-    while (true) {
-        if (tid == 0) s_row = atomicAdd(a.next_row, 1);
+    if (tid == 0) {
+        s_row = atomicAdd(a.next_row, 1);
+        s_stop = ld_flag(a.abort_flag);
+    }
+    __syncthreads();
+    int64_t i = __builtin_amdgcn_readfirstlane(s_row);
+    int stop = __builtin_amdgcn_readfirstlane(s_stop);
+
+    while (i < a.n && !stop) {
         for (int q = tid; q < nwords; q += IT) bits[q] = 0u;
         __syncthreads();
-        const int64_t i = s_row;
-        if (i >= a.n) break;
-        if (__hip_atomic_load(a.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
         const int64_t lo = i - a.lb;
         // 1. row i of A
         const int32_t r0 = a.row_ptr[i], r1 = a.row_ptr[i + 1];
@@ -261,7 +290,9 @@ __global__ __launch_bounds__(IT) void ilut_row_kernel(IlutDevArgs a) {
         int kprev = -1;
         int64_t rlo = -(1ll << 40);     // wave 0: rows rlo..rlo+63 whose flags are cached in rmask
         unsigned long long rmask = 0ull;
-        for (int par = 0;; par ^= 1) {
+        int par = 0;
+        int going = 1;
+        while (going) {
             if (wave == 0) {
                 int found = -1;
                 for (int base = (kprev + 1) >> 5; base <= ((dpos - 1) >> 5) && found < 0; base += 64) {
@@ -294,8 +325,7 @@ __global__ __launch_bounds__(IT) void ilut_row_kernel(IlutDevArgs a) {
                         if (!rdy) {
                             rlo = k;
                             const int64_t r = k + lane;
-                            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-                            rmask = __ballot(r < i && ld_flag(a.ready + r) == (int32_t)a.epoch);
+                            rmask = __ballot(r < i && ld_flag(a.ready + r * FLAG_STRIDE) == (int32_t)a.epoch);
                             rdy = rmask & 1ull;
                             // rows seen finished: their data, read below with ordinary
                             // loads, must not come from lines cached before
@@ -303,7 +333,9 @@ __global__ __launch_bounds__(IT) void ilut_row_kernel(IlutDevArgs a) {
                         }
                         if (!rdy) {
                             int ok = 1;
-                            if (lane == 0) ok = wait_flag(a.ready + k, (int32_t)a.epoch, a.abort_flag, a.wait_ticks, a.status + 2, i, k);
+                            if (lane == 0)
+                                ok = wait_flag(a.ready + k * FLAG_STRIDE, (int32_t)a.epoch, a.abort_flag, a.wait_ticks,
+                                               a.status + 2, i, k);
                             ok = __shfl(ok, 0, 64);
                             if (ok) {
                                 rmask |= 1ull;
@@ -338,21 +370,16 @@ __global__ __launch_bounds__(IT) void ilut_row_kernel(IlutDevArgs a) {
                 }
             }
             __syncthreads();
-            const int kp = s_k[par];
-            if (kp < 0) break;
-            const int fl = s_flag[par];
-            if (fl == -2) {
-                if (tid == 0) {
-                    __hip_atomic_store(a.status + 4, (int32_t)(i + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    __hip_atomic_store(a.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                }
-                break;
-            }
-            if (fl < 0) break;
-            if (fl == 1) {
+            const int kp = __builtin_amdgcn_readfirstlane(s_k[par]);
+            const int fl = __builtin_amdgcn_readfirstlane(s_flag[par]);
+            if (kp < 0 || fl < 0) {
+                going = 0;
+                if (fl == -2) stop = 1;   // recorded below
+                if (fl == -1) stop = 1;   // a wait failed: the launch is being abandoned
+            } else if (fl == 1) {
                 const double mr = s_m[par].x, mi = s_m[par].y;
                 const int64_t ub0 = s_uoff[par];
-                const int len = s_ulen[par];
+                const int len = __builtin_amdgcn_readfirstlane(s_ulen[par]);
                 bool badcol = false;
                 for (int q = 1 + tid; q < len; q += IT) {
                     const int p = (int)(a.u_col[ub0 + q] - lo);
@@ -371,122 +398,134 @@ __global__ __launch_bounds__(IT) void ilut_row_kernel(IlutDevArgs a) {
                         atomicOr(&bits[p >> 5], bit);
                     }
                 }
-                if (__syncthreads_or(badcol)) {
-                    if (tid == 0) {
-                        __hip_atomic_store(a.status + 4, (int32_t)(i + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        __hip_atomic_store(a.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    }
-                    break;
+                if (block_or(badcol, s_or)) {
+                    going = 0;
+                    stop = 1;
+                    if (tid == 0) __hip_atomic_store(a.status + 4, (int32_t)(i + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 }
             }
+            if (stop && fl == -2 && tid == 0)
+                __hip_atomic_store(a.status + 4, (int32_t)(i + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             kprev = kp;
+            par ^= 1;
+            going = __builtin_amdgcn_readfirstlane(going);
+            stop = __builtin_amdgcn_readfirstlane(stop);
         }
-        if (__hip_atomic_load(a.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
-
-        // 3. dropping, cap, output
-        int n_gt_l = 0, n_gt_u = 0;
-        unsigned long long Kl = 0ull, Ku = 0ull;
-        int cl = 0, cu = 0;   // candidate counts per thread
-        for (int p = tid; p < W; p += IT) {
-            if (p == dpos || !((bits[p >> 5] >> (p & 31)) & 1u)) continue;
-            const double2 v = w[p];
-            const double m2 = v.x * v.x + v.y * v.y;
-            if (m2 == 0.0 || m2 < tau2) continue;
-            if (p < dpos) ++cl; else ++cu;
-        }
-        int totl = 0, totu = 0;
-        (void)block_scan(cl, &totl, sbuf);
-        (void)block_scan(cu, &totu, sbuf);
-        const bool cap_l = totl > lfil, cap_u = totu > lfil;
-        // lfil = 0 keeps nothing: K above every key, no ties taken
-        if (cap_l) Kl = lfil > 0 ? select_kth(w, bits, 0, dpos, tau2, lfil, &n_gt_l, hist, sbuf + 4) : ~0ull;
-        if (cap_u) Ku = lfil > 0 ? select_kth(w, bits, dpos + 1, W, tau2, lfil, &n_gt_u, hist, sbuf + 4) : ~0ull;
-        // compaction in column order: each thread takes a contiguous chunk
-        const int chunk = (W + IT - 1) / IT;
-        const int c0 = tid * chunk, c1 = min(W, c0 + chunk);
-        int keep_l = 0, keep_u = 0, eq_l = 0, eq_u = 0;
-        for (int p = c0; p < c1; ++p) {
-            if (p == dpos || !((bits[p >> 5] >> (p & 31)) & 1u)) continue;
-            const double2 v = w[p];
-            const double m2 = v.x * v.x + v.y * v.y;
-            if (m2 == 0.0 || m2 < tau2) continue;
-            const unsigned long long key = key_of(m2);
-            if (p < dpos) {
-                if (!cap_l || key > Kl) ++keep_l; else if (key == Kl) ++eq_l;
-            } else {
-                if (!cap_u || key > Ku) ++keep_u; else if (key == Ku) ++eq_u;
+        if (stop) {
+            if (tid == 0) publish_flag(a.abort_flag, 1);
+        } else {
+            // 3. dropping, cap, output
+            int n_gt_l = 0, n_gt_u = 0;
+            unsigned long long Kl = 0ull, Ku = 0ull;
+            int cl = 0, cu = 0;   // candidate counts per thread
+            for (int p = tid; p < W; p += IT) {
+                if (p == dpos || !((bits[p >> 5] >> (p & 31)) & 1u)) continue;
+                const double2 v = w[p];
+                const double m2 = v.x * v.x + v.y * v.y;
+                if (m2 == 0.0 || m2 < tau2) continue;
+                if (p < dpos) ++cl; else ++cu;
             }
-        }
-        int tmp;
-        const int eq_l_before = block_scan(eq_l, &tmp, sbuf);
-        const int eq_u_before = block_scan(eq_u, &tmp, sbuf);
-        // ties at K: the first (lfil - n_gt) in column order are kept
-        const int take_l = cap_l ? max(0, min(eq_l, lfil - n_gt_l - eq_l_before)) : 0;
-        const int take_u = cap_u ? max(0, min(eq_u, lfil - n_gt_u - eq_u_before)) : 0;
-        int tot_l = 0, tot_u = 0;
-        const int out_l = block_scan(keep_l + take_l, &tot_l, sbuf);
-        const int out_u = block_scan(keep_u + take_u, &tot_u, sbuf);
-        // diagonal, breakdown check
-        double2 dg = make_double2(0.0, 0.0);
-        if ((bits[dpos >> 5] >> (dpos & 31)) & 1u) dg = w[dpos];
-        const int64_t lb0 = a.l_off[i], ub0 = a.u_off[i];
-        int written_l = 0, written_u = 0, el = 0, eu = 0;
-        bool bad = false;
-        for (int p = c0; p < c1; ++p) {
-            if (p == dpos || !((bits[p >> 5] >> (p & 31)) & 1u)) continue;
-            const double2 v = w[p];
-            const double m2 = v.x * v.x + v.y * v.y;
-            if (m2 == 0.0 || m2 < tau2) continue;
-            const unsigned long long key = key_of(m2);
-            const int32_t c = (int32_t)(lo + p);
-            if (p < dpos) {
-                bool keep = !cap_l || key > Kl;
-                if (cap_l && key == Kl) keep = el++ < take_l;
-                if (keep) {
-                    wt_store(a.l_col + lb0 + out_l + written_l, c);
-                    wt_store(a.l_val + lb0 + out_l + written_l, v);
-                    ++written_l;
-                }
-            } else {
-                bool keep = !cap_u || key > Ku;
-                if (cap_u && key == Ku) keep = eu++ < take_u;
-                if (keep) {
-                    if (!isfinite(v.x) || !isfinite(v.y)) bad = true;
-                    wt_store(a.u_col + ub0 + 1 + out_u + written_u, c);
-                    wt_store(a.u_val + ub0 + 1 + out_u + written_u, v);
-                    ++written_u;
+            int totl = 0, totu = 0;
+            (void)block_scan(cl, &totl, sbuf);
+            (void)block_scan(cu, &totu, sbuf);
+            const bool cap_l = totl > lfil, cap_u = totu > lfil;
+            // lfil = 0 keeps nothing: K above every key, no ties taken
+            if (cap_l) Kl = lfil > 0 ? select_kth(w, bits, 0, dpos, tau2, lfil, &n_gt_l, hist, sbuf + 4) : ~0ull;
+            if (cap_u) Ku = lfil > 0 ? select_kth(w, bits, dpos + 1, W, tau2, lfil, &n_gt_u, hist, sbuf + 4) : ~0ull;
+            // compaction in column order: each thread takes a contiguous chunk
+            const int chunk = (W + IT - 1) / IT;
+            const int c0 = tid * chunk, c1 = min(W, c0 + chunk);
+            int keep_l = 0, keep_u = 0, eq_l = 0, eq_u = 0;
+            for (int p = c0; p < c1; ++p) {
+                if (p == dpos || !((bits[p >> 5] >> (p & 31)) & 1u)) continue;
+                const double2 v = w[p];
+                const double m2 = v.x * v.x + v.y * v.y;
+                if (m2 == 0.0 || m2 < tau2) continue;
+                const unsigned long long key = key_of(m2);
+                if (p < dpos) {
+                    if (!cap_l || key > Kl) ++keep_l; else if (key == Kl) ++eq_l;
+                } else {
+                    if (!cap_u || key > Ku) ++keep_u; else if (key == Ku) ++eq_u;
                 }
             }
-        }
-        if (tid == 0) {
-            if (!isfinite(dg.x) || !isfinite(dg.y)) bad = true;
-            const double fl = 1e-14 * rowinf;
-            const double dmag = sqrt(dg.x * dg.x + dg.y * dg.y);
-            if (!bad && (dmag < fl || dmag == 0.0)) {
-                if (dmag > 0.0) dg = make_double2(fl * dg.x / dmag, fl * dg.y / dmag);
-                else if (fl > 0.0) dg = make_double2(fl, 0.0);
-                else dg = make_double2(1.0, 0.0);
-                atomicAdd(a.status + 1, 1);
+            int tmp;
+            const int eq_l_before = block_scan(eq_l, &tmp, sbuf);
+            const int eq_u_before = block_scan(eq_u, &tmp, sbuf);
+            // ties at K: the first (lfil - n_gt) in column order are kept
+            const int take_l = cap_l ? max(0, min(eq_l, lfil - n_gt_l - eq_l_before)) : 0;
+            const int take_u = cap_u ? max(0, min(eq_u, lfil - n_gt_u - eq_u_before)) : 0;
+            int tot_l = 0, tot_u = 0;
+            const int out_l = block_scan(keep_l + take_l, &tot_l, sbuf);
+            const int out_u = block_scan(keep_u + take_u, &tot_u, sbuf);
+            // diagonal, breakdown check
+            double2 dg = make_double2(0.0, 0.0);
+            if ((bits[dpos >> 5] >> (dpos & 31)) & 1u) dg = w[dpos];
+            const int64_t lb0 = a.l_off[i], ub0 = a.u_off[i];
+            int written_l = 0, written_u = 0, el = 0, eu = 0;
+            bool bad = false;
+            for (int p = c0; p < c1; ++p) {
+                if (p == dpos || !((bits[p >> 5] >> (p & 31)) & 1u)) continue;
+                const double2 v = w[p];
+                const double m2 = v.x * v.x + v.y * v.y;
+                if (m2 == 0.0 || m2 < tau2) continue;
+                const unsigned long long key = key_of(m2);
+                const int32_t c = (int32_t)(lo + p);
+                if (p < dpos) {
+                    bool keep = !cap_l || key > Kl;
+                    if (cap_l && key == Kl) keep = el++ < take_l;
+                    if (keep) {
+                        a.l_col[lb0 + out_l + written_l] = c;
+                        a.l_val[lb0 + out_l + written_l] = v;
+                        ++written_l;
+                    }
+                } else {
+                    bool keep = !cap_u || key > Ku;
+                    if (cap_u && key == Ku) keep = eu++ < take_u;
+                    if (keep) {
+                        if (!isfinite(v.x) || !isfinite(v.y)) bad = true;
+                        a.u_col[ub0 + 1 + out_u + written_u] = c;
+                        a.u_val[ub0 + 1 + out_u + written_u] = v;
+                        ++written_u;
+                    }
+                }
             }
-            wt_store(a.u_col + ub0, (int32_t)i);
-            wt_store(a.u_val + ub0, dg);
-            wt_store(a.udiag + i, dg);
-            wt_store(a.l_len + i, tot_l);
-            wt_store(a.u_len + i, tot_u + 1);
-        }
-        if (__syncthreads_or(bad)) {
             if (tid == 0) {
-                atomicCAS(a.status, 0, (int32_t)(i + 1));
-                __hip_atomic_store(a.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (!isfinite(dg.x) || !isfinite(dg.y)) bad = true;
+                const double fl = 1e-14 * rowinf;
+                const double dmag = sqrt(dg.x * dg.x + dg.y * dg.y);
+                if (!bad && (dmag < fl || dmag == 0.0)) {
+                    if (dmag > 0.0) dg = make_double2(fl * dg.x / dmag, fl * dg.y / dmag);
+                    else if (fl > 0.0) dg = make_double2(fl, 0.0);
+                    else dg = make_double2(1.0, 0.0);
+                    atomicAdd(a.status + 1, 1);
+                }
+                a.u_col[ub0] = (int32_t)i;
+                a.u_val[ub0] = dg;
+                a.udiag[i] = dg;
+                a.l_len[i] = tot_l;
+                a.u_len[i] = tot_u + 1;
             }
-            break;
+            if (block_or(bad, s_or)) {
+                stop = 1;
+                if (tid == 0) {
+                    atomicCAS(a.status, 0, (int32_t)(i + 1));
+                    publish_flag(a.abort_flag, 1);
+                }
+            } else if (tid == 0) {
+                // the release writes the row back from L2 before the flag
+                publish_flag(a.ready + i * FLAG_STRIDE, (int32_t)a.epoch);
+                if ((i & 4095) == 0) __hip_atomic_store(a.host_progress, (int32_t)i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            }
         }
-        __builtin_amdgcn_s_waitcnt(0);
+        // next row
         __syncthreads();
         if (tid == 0) {
-            __hip_atomic_store(a.ready + i, (int32_t)a.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if ((i & 4095) == 0) __hip_atomic_store(a.host_progress, (int32_t)i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            s_row = atomicAdd(a.next_row, 1);
+            s_stop = ld_flag(a.abort_flag);
         }
+        __syncthreads();
+        i = __builtin_amdgcn_readfirstlane(s_row);
+        stop = __builtin_amdgcn_readfirstlane(stop | s_stop);
     }
 }
 
@@ -539,9 +578,9 @@ om_status ilut_factor_gpu(const om_csr* A, int item, double drop_tol, double fil
     OM_TRY(lval.alloc(std::max<int64_t>(1, loff[n])));
     OM_TRY(ucol.alloc(uoff[n]));
     OM_TRY(uval.alloc(uoff[n]));
-    OM_TRY(ready.alloc(n));
+    OM_TRY(ready.alloc((size_t)n * FLAG_STRIDE));
     OM_TRY(udiag.alloc(n));
-    OM_TRY(misc.alloc(8));
+    OM_TRY(misc.alloc(64));   // [0] row counter, [1..15] status, [32] abort flag (a line of its own)
     const int64_t wstride = (W + 7) & ~7ll;
     OM_TRY(work.alloc((size_t)G * wstride));
     OM_HIP(hipMemsetAsync(ready.p, 0, ready.bytes(), s));
@@ -555,8 +594,10 @@ om_status ilut_factor_gpu(const om_csr* A, int item, double drop_tol, double fil
     a.l_off = dloff.p; a.u_off = duoff.p; a.l_len = llen.p; a.u_len = ulen.p;
     a.l_col = lcol.p; a.l_val = lval.p; a.u_col = ucol.p; a.u_val = uval.p;
     a.udiag = udiag.p; a.ready = ready.p; a.epoch = 1; a.work = work.p;
-    a.wait_ticks = (long long)std::max(clk_khz, 1000) * 1000ll * 30;   // 30 s
-    a.next_row = misc.p; a.abort_flag = misc.p + 1; a.status = misc.p + 2;
+    double wait_s = 30.0;   // bound of one wait (OMSS_ILUT_WAIT_S)
+    if (const char* e = getenv("OMSS_ILUT_WAIT_S")) wait_s = std::max(0.1, atof(e));
+    a.wait_ticks = (long long)((double)std::max(clk_khz, 1000) * 1000.0 * wait_s);
+    a.next_row = misc.p; a.abort_flag = misc.p + 32; a.status = misc.p + 2;
     // progress word in pinned host memory, written by the kernel now and then
     int32_t* hprog = nullptr;
     OM_HIP(hipHostMalloc((void**)&hprog, 256, hipHostMallocMapped | hipHostMallocCoherent));
@@ -566,9 +607,15 @@ om_status ilut_factor_gpu(const om_csr* A, int item, double drop_tol, double fil
     void* args[] = {(void*)&a};
     const bool verbose = std::getenv("OMSS_VERBOSE") != nullptr;
     const auto t0 = std::chrono::steady_clock::now();
-    OM_HIP(hipLaunchCooperativeKernel((const void*)ilut_row_kernel, dim3(G), dim3(IT), args, 0, s));
-    int32_t hs[8];
-    OM_HIP(hipMemcpyAsync(hs, misc.p, sizeof hs, hipMemcpyDeviceToHost, s));
+    // rows are handed out dynamically, so the blocks need not be co-resident:
+    // an ordinary launch (OMSS_ILUT_COOP=1 selects a cooperative one)
+    const char* ce = getenv("OMSS_ILUT_COOP");
+    if (ce && atoi(ce) == 1) {
+        OM_HIP(hipLaunchCooperativeKernel((const void*)ilut_row_kernel, dim3(G), dim3(IT), args, 0, s));
+    } else {
+        hipLaunchKernelGGL(ilut_row_kernel, dim3(G), dim3(IT), 0, s, a);
+        OM_HIP(hipGetLastError());
+    }
     double next_report = 20.0;
     while (true) {
         const hipError_t q = hipStreamQuery(s);
@@ -582,6 +629,8 @@ om_status ilut_factor_gpu(const om_csr* A, int item, double drop_tol, double fil
             next_report += 20.0;
         }
     }
+    int32_t hs[64];
+    OM_HIP(hipMemcpyAsync(hs, misc.p, sizeof hs, hipMemcpyDeviceToHost, s));
     OM_HIP(hipStreamSynchronize(s));
     if (verbose)
         fprintf(stderr, "[omss] device ILUT: n %lld, window %lld, %d workgroups, %.3f s\n", (long long)n, (long long)W, G,
@@ -595,17 +644,17 @@ om_status ilut_factor_gpu(const om_csr* A, int item, double drop_tol, double fil
         set_error("device ILUT: inconsistent row data met while eliminating row %d", hs[6] - 1);
         return OM_EHIP;
     }
-    if (hs[1] != 0) {
+    if (hs[32] != 0) {
         std::vector<int32_t> rd(n);
-        OM_HIP(hipMemcpy(rd.data(), ready.p, n * sizeof(int32_t), hipMemcpyDeviceToHost));
+        OM_HIP(hipMemcpy2D(rd.data(), sizeof(int32_t), ready.p, FLAG_STRIDE * sizeof(int32_t), sizeof(int32_t), n,
+                           hipMemcpyDeviceToHost));
         int64_t published = 0, first_missing = -1;
         for (int64_t r = 0; r < n; ++r) {
             if (rd[r] == 1) ++published;
             else if (first_missing < 0) first_missing = r;
         }
         set_error("device ILUT: a wait timed out (row %d waited for row %d; %lld of %lld rows published, first "
-                  "missing %lld, %d rows handed out)", hs[4] - 1, hs[5] - 1, (long long)published, (long long)n,
-                  (long long)first_missing, hs[0]);
+                  "missing %lld)", hs[4] - 1, hs[5] - 1, (long long)published, (long long)n, (long long)first_missing);
         return OM_ETIMEOUT;
     }
     // gather the rows into the host CSR factor

@@ -291,12 +291,6 @@ def _bits(M):
     return M.view(np.uint64)
 
 
-DEVICE_ILUT_SKIP = pytest.mark.skip(
-    reason="device ILUT (opt-in, OMSS_ILUT=device): rows that eliminate against other rows time out "
-           "waiting for their ready flags; cause under investigation")
-
-
-@DEVICE_ILUT_SKIP
 @pytest.mark.parametrize("ci", range(len(ILUT_CASES)))
 def test_device_ilut_is_the_host_factor_bit_for_bit(ci, monkeypatch):
     """The row-pipelined device ILUT (Sec. II dropping rules) yields exactly
@@ -319,7 +313,6 @@ def test_device_ilut_is_the_host_factor_bit_for_bit(ci, monkeypatch):
     assert np.array_equal(_bits(L2.data), _bits(Lg.data)) and np.array_equal(_bits(U2.data), _bits(Ug.data))
 
 
-@DEVICE_ILUT_SKIP
 def test_device_ilut_batch_items_are_factored_independently(monkeypatch):
     monkeypatch.setenv("OMSS_ILUT", "device")
     ps = [W.TINY.replace(nc=4, nm=9, E=e) for e in (0.15, 0.45, 0.3)]
