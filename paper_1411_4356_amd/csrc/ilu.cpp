@@ -83,11 +83,11 @@ om_status ilu_factor_impl(const om_csr* Ain, double drop_tol, double fill_factor
     std::vector<om_status> status(NF, OM_OK);
     std::vector<std::string> errs(NF);
     std::vector<int64_t> nl(NF), nu(NF), dl(NF), du(NF), rep(NF);
-    // Factorisation: on host threads (items concurrently), or with
-    // OMSS_ILUT=device on the device (one item at a time, the whole GPU) unless
-    // the band is wider than the device kernel's window.
+    // Factorisation: on the device (one item at a time, the whole GPU), or on
+    // host threads (items concurrently) with OMSS_ILUT=host or when the band
+    // is wider than the device kernel's window.
     const char* ie = std::getenv("OMSS_ILUT");
-    bool on_device = ie && std::strcmp(ie, "device") == 0;
+    bool on_device = !(ie && std::strcmp(ie, "host") == 0);
     std::vector<std::unique_ptr<HostFactor>> dev_factors(NF);
     if (on_device) {
         for (int b = 0; b < NF && on_device; ++b) {

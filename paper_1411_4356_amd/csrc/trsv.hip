@@ -108,7 +108,7 @@ __global__ __launch_bounds__(64 * TW) void trsv_chain_kernel(const TriView<VT>* 
     const TriView<VT> S = views[b * 4 + kind];
     const VT* y = rhs + (int64_t)b * n;
     VT* x = out + (int64_t)b * n;
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     __shared__ VT part[TW][64];
     __shared__ VT tri[TRI_N];
@@ -188,6 +188,24 @@ __device__ inline void raise_abort(int32_t* f) {
     __hip_atomic_store(f, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Control flow around barriers depends only on wave-uniform values
+// (readfirstlane), so that every wave executes the same barriers.
+__device__ inline int64_t rfl64(int64_t v) {
+    const int lo = __builtin_amdgcn_readfirstlane((int)(v & 0xffffffffll));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(v >> 32));
+    return ((int64_t)hi << 32) | (uint32_t)lo;
+}
+
+__device__ inline int block_or(bool v, int* buf) {
+    const unsigned long long b = __ballot(v);
+    if ((threadIdx.x & 63) == 0) buf[threadIdx.x >> 6] = b != 0ull;
+    __syncthreads();
+    int r = 0;
+    for (int w = 0; w < TW; ++w) r |= buf[w];
+    __syncthreads();
+    return __builtin_amdgcn_readfirstlane(r);
+}
+
 // Wait until *p >= target; returns the observed value or -1 on timeout/abort.
 __device__ inline int64_t wait_ge64(const int64_t* p, int64_t target, int32_t* abort_flag) {
     long long spins = 0;
@@ -221,6 +239,7 @@ struct CoopShared {
     VT mid[2][TW - 1][64];
     VT ring[RING];
     int fail;
+    int orbuf[TW];
 };
 
 template <typename VT>
@@ -243,7 +262,7 @@ __global__ __launch_bounds__(64 * TW) void trsv_coop_kernel(const TriView<VT>* _
     if (active && !active[b]) return;
     const TriView<VT> S = views[b * 4 + kind];
     VT* x = out + (int64_t)b * n;
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     VT* far_buf = reinterpret_cast<VT*>(a.far_buf) + (int64_t)b * S.nblk * 64;
     int32_t* fdone = a.fdone + (int64_t)b * S.nblk;
@@ -267,7 +286,9 @@ __global__ __launch_bounds__(64 * TW) void trsv_coop_kernel(const TriView<VT>* _
                 for (int j = 0; j < FU; ++j)
                     if (j < cnt) needmax = needmax > S.far_need[c0 + j] ? needmax : (int64_t)S.far_need[c0 + j];
                 if (needmax + 2 > known) {
-                    const int64_t v = wait_ge64(progress, ep + needmax + 1, a.abort_flag);
+                    // every lane waits for the same target; the result is made
+                    // wave-uniform so that the loop exits uniformly
+                    const int64_t v = rfl64(wait_ge64(progress, ep + needmax + 1, a.abort_flag));
                     if (v < 0) { ok = false; break; }
                     known = v - ep;
                 }
@@ -294,7 +315,7 @@ __global__ __launch_bounds__(64 * TW) void trsv_coop_kernel(const TriView<VT>* _
                     if (j < cnt) cfma(acc, vv[j], xv[j]);
             }
             sh.part[wave][lane] = acc;
-            if (__syncthreads_or(!ok)) return;
+            if (block_or(!ok, sh.orbuf)) return;
             if (wave == 0) {
                 VT t = sh.part[0][lane];
 #pragma unroll
@@ -354,7 +375,7 @@ __global__ __launch_bounds__(64 * TW) void trsv_coop_kernel(const TriView<VT>* _
             if (a.tstat) { const unsigned long long tC = wall_clock64(); t_near += tB - tA; t_wait += tC - tB; tA = tC; }
         }
         __syncthreads();
-        if (sh.fail) return;
+        if (__builtin_amdgcn_readfirstlane(sh.fail)) return;
         if (wave == 0) {
             const int64_t row = g * 64 + lane;
             const bool valid = row < n;
