@@ -156,6 +156,11 @@ struct TrsvScratch {
     DevBuf<int64_t> progress;   // batch, (epoch << 32) | blocks done
     DevBuf<int32_t> abort_flag; // 1 word
     uint32_t epoch = 0;
+    // solves of several right-hand sides with one shared factor
+    DevBuf<double2> m_far;      // nblk * batch * 64 partial sums
+    DevBuf<double2> m_x;        // n * batch: the solution in solve order, interleaved
+    DevBuf<int32_t> m_fdone;    // nblk, epoch tags
+    DevBuf<int64_t> m_progress; // (epoch << 32) | blocks done
 };
 
 }  // namespace omss

@@ -1,5 +1,5 @@
-// ilu_factor: host ILUT of every batch item (one host thread per item), solve
-// schedules, upload of the factors to the device.
+// ilu_factor: ILUT of every batch item (on the device, or on host threads, one
+// per item), and the solve schedules of the factors.
 #include <algorithm>
 #include <chrono>
 #include <cstdio>
@@ -88,16 +88,60 @@ om_status ilu_factor_impl(const om_csr* Ain, double drop_tol, double fill_factor
     // is wider than the device kernel's window.
     const char* ie = std::getenv("OMSS_ILUT");
     bool on_device = !(ie && std::strcmp(ie, "host") == 0);
-    std::vector<std::unique_ptr<HostFactor>> dev_factors(NF);
+    // host-side schedule build of the given kinds of a host factor, concurrently
+    auto host_schedules = [&](const HostFactor& F, int b, int k0, int k1) -> om_status {
+        std::vector<std::thread> kt;
+        std::vector<om_status> krc(4, OM_OK);
+        std::vector<std::string> kerr(4);
+        for (int k = k0; k < k1; ++k)
+            kt.emplace_back([&, k] {
+                (void)hipSetDevice(dev);
+                SolveCSR S;
+                factor_to_solve(F, k, S);
+                HostTri H;
+                build_host_tri(S, H);
+                S = SolveCSR();
+                if (k == 0) dl[b] = H.depth;
+                if (k == 1) du[b] = H.depth;
+                krc[k] = upload_tri(H, c64, M->sched[(size_t)b * 4 + k]);
+                if (krc[k] != OM_OK) kerr[k] = last_error();
+            });
+        for (auto& x : kt) x.join();
+        for (int k = k0; k < k1; ++k)
+            if (krc[k] != OM_OK) { set_error("%s", kerr[k].c_str()); return krc[k]; }
+        return OM_OK;
+    };
     if (on_device) {
-        for (int b = 0; b < NF && on_device; ++b) {
-            dev_factors[b].reset(new HostFactor);
+        // the factor stays on the device: L and U schedules are built there;
+        // the adjoint solves (transposes) and a kept host copy go through the host
+        for (int b = 0; b < NF; ++b) {
+            DevFactor D;
             std::string err;
-            const om_status rc = ilut_factor_gpu(A, b, drop_tol, fill_factor, dev_factors[b].get(), &err, s);
+            const om_status rc = ilut_factor_dev(A, b, drop_tol, fill_factor, &D, &err, s);
             if (rc == OM_EBREAKDOWN) { set_error("batch item %d: %s", b, err.c_str()); return rc; }
             if (rc == OM_EINVAL && b == 0) { on_device = false; break; }   // band too wide: host threads
             if (rc != OM_OK) return rc;
-            if (verbose) fprintf(stderr, "[omss] ilu_factor: item %d factored on the device\n", b);
+            nl[b] = D.nnz_l;
+            nu[b] = D.nnz_u;
+            rep[b] = D.repaired;
+            dl[b] = du[b] = -1;
+            if (verbose)
+                fprintf(stderr, "[omss] ilu_factor: item %d factored on the device (fill %.1f)\n", b,
+                        (double)(nl[b] + nu[b]) / (double)nnz);
+            // OMSS_ILU_SCHED=host builds every schedule on the host (a cross-check)
+            const char* se = std::getenv("OMSS_ILU_SCHED");
+            const bool host_lu = se && std::strcmp(se, "host") == 0;
+            if (!host_lu) {
+                OM_TRY(build_tri_device(D, 0, c64, M->sched[(size_t)b * 4 + 0], s));
+                OM_TRY(build_tri_device(D, 1, c64, M->sched[(size_t)b * 4 + 1], s));
+            }
+            if (host_lu || adjoint || (flags & OM_ILU_KEEP_HOST)) {
+                std::unique_ptr<HostFactor> F(new HostFactor);
+                OM_TRY(devfactor_to_host(D, F.get(), s));
+                if (host_lu || adjoint) OM_TRY(host_schedules(*F, b, host_lu ? 0 : 2, adjoint ? 4 : 2));
+                if (flags & OM_ILU_KEEP_HOST) M->host[b] = std::move(F);
+            }
+            if (verbose) fprintf(stderr, "[omss] ilu_factor: item %d schedules built\n", b);
         }
     }
     const int HT = host_threads();
@@ -106,19 +150,13 @@ om_status ilu_factor_impl(const om_csr* Ain, double drop_tol, double fill_factor
     auto work = [&](int t) {
         (void)hipSetDevice(dev);
         for (int b = t; b < NF; b += T) {
-            std::unique_ptr<HostFactor> F;
+            std::unique_ptr<HostFactor> F(new HostFactor);
             std::string err;
-            int rc = 0;
-            if (on_device) {
-                F = std::move(dev_factors[b]);
-            } else {
-                F.reset(new HostFactor);
-                rc = per_item > 1
-                    ? ilut_factor_host_mt(n, A->h_row_ptr.data(), A->h_col.data(), vals.data() + (size_t)b * nnz * 2,
-                                          drop_tol, fill_factor, per_item, F.get(), &err)
-                    : ilut_factor_host(n, A->h_row_ptr.data(), A->h_col.data(), vals.data() + (size_t)b * nnz * 2,
-                                       drop_tol, fill_factor, 0.0, F.get(), &err);
-            }
+            const int rc = per_item > 1
+                ? ilut_factor_host_mt(n, A->h_row_ptr.data(), A->h_col.data(), vals.data() + (size_t)b * nnz * 2,
+                                      drop_tol, fill_factor, per_item, F.get(), &err)
+                : ilut_factor_host(n, A->h_row_ptr.data(), A->h_col.data(), vals.data() + (size_t)b * nnz * 2,
+                                   drop_tol, fill_factor, 0.0, F.get(), &err);
             if (rc != 0) {
                 status[b] = OM_EBREAKDOWN;
                 errs[b] = "batch item " + std::to_string(b) + ": " + err;
@@ -131,34 +169,18 @@ om_status ilu_factor_impl(const om_csr* Ain, double drop_tol, double fill_factor
                 fprintf(stderr, "[omss] ilu_factor: item %d factored (fill %.1f), building solve schedules\n", b,
                         (double)(nl[b] + nu[b]) / (double)nnz);
             // the solve schedules of the factor are independent: build them concurrently
-            const int nk = adjoint ? 4 : 2;
-            std::vector<std::thread> kt;
-            std::vector<om_status> krc(nk, OM_OK);
-            std::vector<std::string> kerr(nk);
-            for (int k = 0; k < nk; ++k)
-                kt.emplace_back([&, k] {
-                    (void)hipSetDevice(dev);
-                    SolveCSR S;
-                    factor_to_solve(*F, k, S);
-                    HostTri H;
-                    build_host_tri(S, H);
-                    S = SolveCSR();
-                    if (k == 0) dl[b] = H.depth;
-                    if (k == 1) du[b] = H.depth;
-                    krc[k] = upload_tri(H, c64, M->sched[(size_t)b * 4 + k]);
-                    if (krc[k] != OM_OK) kerr[k] = last_error();
-                });
-            for (auto& x : kt) x.join();
-            for (int k = 0; k < nk; ++k)
-                if (krc[k] != OM_OK) { status[b] = krc[k]; errs[b] = kerr[k]; return; }
+            const om_status krc = host_schedules(*F, b, 0, adjoint ? 4 : 2);
+            if (krc != OM_OK) { status[b] = krc; errs[b] = last_error(); return; }
             if (verbose) fprintf(stderr, "[omss] ilu_factor: item %d schedules uploaded\n", b);
             if (flags & OM_ILU_KEEP_HOST) M->host[b] = std::move(F);
         }
     };
-    std::vector<std::thread> th;
-    for (int t = 1; t < T; ++t) th.emplace_back(work, t);
-    work(0);
-    for (auto& x : th) x.join();
+    if (!on_device) {
+        std::vector<std::thread> th;
+        for (int t = 1; t < T; ++t) th.emplace_back(work, t);
+        work(0);
+        for (auto& x : th) x.join();
+    }
     for (int b = 0; b < NF; ++b)
         if (status[b] != OM_OK) { set_error("%s", errs[b].c_str()); return status[b]; }
     OM_TRY(finish_views(M.get(), s));

@@ -34,6 +34,7 @@
 #include <vector>
 
 #include "common.hpp"
+#include "ilu.hpp"
 #include "ilut.hpp"
 #include "kernels.hpp"
 
@@ -45,7 +46,8 @@ constexpr int IT = 256;             // threads per workgroup
 constexpr int IWAVES = IT / 64;
 constexpr int WBITS_MAX = 1 << 16;  // largest band window (lb + ub + 1)
 constexpr int RADIX_BITS = 11;
-constexpr int FLAG_STRIDE = 32;     // one 128-byte line per row's ready flag
+constexpr int FLAG_STRIDE = 32;
+constexpr int UF = 4;               // U-row entries per thread in flight in an update     // one 128-byte line per row's ready flag
 constexpr int RADIX = 1 << RADIX_BITS;
 
 struct IlutDevArgs {
@@ -345,7 +347,10 @@ __global__ __launch_bounds__(IT) void ilut_row_kernel(IlutDevArgs a) {
                             }
                         }
                         if (flag == 0) {
+                            // pivot, offset and length of row k in one round of loads
                             const double2 d = ld_coh(a.udiag + k);
+                            const int64_t uo = a.u_off[k], uo1 = a.u_off[k + 1];
+                            const int ul = ld_flag(a.u_len + k);
                             const double den = d.x * d.x + d.y * d.y;
                             mr = (x.x * d.x + x.y * d.y) / den;
                             mi = (x.y * d.x - x.x * d.y) / den;
@@ -354,9 +359,9 @@ __global__ __launch_bounds__(IT) void ilut_row_kernel(IlutDevArgs a) {
                             } else {
                                 if (lane == 0) w[found] = make_double2(mr, mi);
                                 flag = 1;
-                                uoff = a.u_off[k];
-                                ulen = ld_flag(a.u_len + k);
-                                if (ulen < 1 || uoff + ulen > a.u_off[k + 1]) flag = -2;
+                                uoff = uo;
+                                ulen = ul;
+                                if (ulen < 1 || uoff + ulen > uo1) flag = -2;
                             }
                         }
                     }
@@ -381,21 +386,55 @@ __global__ __launch_bounds__(IT) void ilut_row_kernel(IlutDevArgs a) {
                 const int64_t ub0 = s_uoff[par];
                 const int len = __builtin_amdgcn_readfirstlane(s_ulen[par]);
                 bool badcol = false;
-                for (int q = 1 + tid; q < len; q += IT) {
-                    const int p = (int)(a.u_col[ub0 + q] - lo);
-                    if (p <= kp || p >= W) { badcol = true; continue; }
-                    const double2 u = a.u_val[ub0 + q];
-                    const double pr = mr * u.x - mi * u.y;
-                    const double pi = mr * u.y + mi * u.x;
-                    const uint32_t bit = 1u << (p & 31);
-                    if (bits[p >> 5] & bit) {
-                        double2 c = w[p];
-                        c.x -= pr;
-                        c.y -= pi;
-                        w[p] = c;
-                    } else {
-                        w[p] = make_double2(-pr, -pi);
-                        atomicOr(&bits[p >> 5], bit);
+                // UF entries per thread at a time: all their loads are issued
+                // before any is used (the columns of a U row are distinct, so
+                // the updates of one step never meet)
+                for (int q0 = 1 + tid; q0 < len; q0 += IT * UF) {
+                    int pc[UF];
+                    double2 uv[UF];
+#pragma unroll
+                    for (int j = 0; j < UF; ++j) {
+                        const int q = q0 + j * IT;
+                        pc[j] = -1;
+                        if (q < len) {
+                            pc[j] = a.u_col[ub0 + q];
+                            uv[j] = a.u_val[ub0 + q];
+                        }
+                    }
+                    bool have[UF];
+                    double2 wv[UF];
+#pragma unroll
+                    for (int j = 0; j < UF; ++j) {
+                        have[j] = false;
+                        if (q0 + j * IT < len) {
+                            const int p = (int)(pc[j] - lo);
+                            if (p <= kp || p >= W) {
+                                badcol = true;
+                                pc[j] = -1;
+                            } else {
+                                pc[j] = p;
+                                have[j] = (bits[p >> 5] >> (p & 31)) & 1u;
+                                if (have[j]) wv[j] = w[p];
+                            }
+                        } else {
+                            pc[j] = -1;
+                        }
+                    }
+#pragma unroll
+                    for (int j = 0; j < UF; ++j) {
+                        const int p = pc[j];
+                        if (p < 0) continue;
+                        const double pr = mr * uv[j].x - mi * uv[j].y;
+                        const double pi = mr * uv[j].y + mi * uv[j].x;
+                        if (have[j]) {
+                            double2 c = wv[j];
+                            c.x -= pr;
+                            c.y -= pi;
+                            w[p] = c;
+                        } else {
+                            w[p] = make_double2(-pr, -pi);
+                            atomicOr(&bits[p >> 5], 1u << (p & 31));
+                        }
                     }
                 }
                 if (block_or(badcol, s_or)) {
@@ -531,7 +570,7 @@ __global__ __launch_bounds__(IT) void ilut_row_kernel(IlutDevArgs a) {
 
 // Factor item `item` of A on the device; the CSR factor is returned on the
 // host in F (same layout as ilut_factor_host).
-om_status ilut_factor_gpu(const om_csr* A, int item, double drop_tol, double fill_factor, HostFactor* F,
+om_status ilut_factor_dev(const om_csr* A, int item, double drop_tol, double fill_factor, DevFactor* D,
                           std::string* err, hipStream_t s) {
     const int64_t n = A->n;
     om_csr* Am = const_cast<om_csr*>(A);
@@ -567,11 +606,19 @@ om_status ilut_factor_gpu(const om_csr* A, int item, double drop_tol, double fil
     if (!coop || per < 1) { set_error("cooperative launch unavailable for the device ILUT"); return OM_EINVAL; }
     int G = (int)std::min<int64_t>((int64_t)cus * per, std::max<int64_t>(1, n));
     if (const char* e = getenv("OMSS_ILUT_GRID")) G = std::max(1, std::min(G, atoi(e)));
-    DevBuf<int64_t> dloff, duoff;
+    DevBuf<int64_t>& dloff = D->l_off;
+    DevBuf<int64_t>& duoff = D->u_off;
     OM_TRY(dloff.upload(loff.data(), loff.size(), s));
     OM_TRY(duoff.upload(uoff.data(), uoff.size(), s));
-    DevBuf<int32_t> llen, ulen, lcol, ucol, ready, misc;
-    DevBuf<double2> lval, uval, work, udiag;
+    DevBuf<int32_t>& llen = D->l_len;
+    DevBuf<int32_t>& ulen = D->u_len;
+    DevBuf<int32_t>& lcol = D->l_col;
+    DevBuf<int32_t>& ucol = D->u_col;
+    DevBuf<double2>& lval = D->l_val;
+    DevBuf<double2>& uval = D->u_val;
+    D->n = n;
+    DevBuf<int32_t> ready, misc;
+    DevBuf<double2> work, udiag;
     OM_TRY(llen.alloc(n));
     OM_TRY(ulen.alloc(n));
     OM_TRY(lcol.alloc(std::max<int64_t>(1, loff[n])));
@@ -657,16 +704,38 @@ om_status ilut_factor_gpu(const om_csr* A, int item, double drop_tol, double fil
                   "missing %lld)", hs[4] - 1, hs[5] - 1, (long long)published, (long long)n, (long long)first_missing);
         return OM_ETIMEOUT;
     }
-    // gather the rows into the host CSR factor
+    // entry counts
+    {
+        std::vector<int32_t> hl(n), hu(n);
+        OM_HIP(hipMemcpyAsync(hl.data(), llen.p, n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        OM_HIP(hipMemcpyAsync(hu.data(), ulen.p, n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        OM_HIP(hipStreamSynchronize(s));
+        D->nnz_l = D->nnz_u = 0;
+        for (int64_t r = 0; r < n; ++r) {
+            D->nnz_l += hl[r];
+            D->nnz_u += hu[r];
+        }
+    }
+    D->repaired = hs[3];
+    return OM_OK;
+}
+
+// Copy of a device factor into the host CSR layout of ilut_factor_host.
+om_status devfactor_to_host(const DevFactor& D, HostFactor* F, hipStream_t s) {
+    const int64_t n = D.n;
+    std::vector<int64_t> loff(n + 1), uoff(n + 1);
     std::vector<int32_t> hl(n), hu(n);
-    OM_HIP(hipMemcpyAsync(hl.data(), llen.p, n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    OM_HIP(hipMemcpyAsync(hu.data(), ulen.p, n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    std::vector<int32_t> acol(std::max<int64_t>(1, loff[n])), bcol(uoff[n]);
-    std::vector<double2> aval(std::max<int64_t>(1, loff[n])), bval(uoff[n]);
-    OM_HIP(hipMemcpyAsync(acol.data(), lcol.p, loff[n] * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    OM_HIP(hipMemcpyAsync(aval.data(), lval.p, loff[n] * sizeof(double2), hipMemcpyDeviceToHost, s));
-    OM_HIP(hipMemcpyAsync(bcol.data(), ucol.p, uoff[n] * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    OM_HIP(hipMemcpyAsync(bval.data(), uval.p, uoff[n] * sizeof(double2), hipMemcpyDeviceToHost, s));
+    OM_HIP(hipMemcpyAsync(loff.data(), D.l_off.p, (n + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    OM_HIP(hipMemcpyAsync(uoff.data(), D.u_off.p, (n + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    OM_HIP(hipMemcpyAsync(hl.data(), D.l_len.p, n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    OM_HIP(hipMemcpyAsync(hu.data(), D.u_len.p, n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    OM_HIP(hipStreamSynchronize(s));
+    std::vector<int32_t> acol(std::max<int64_t>(1, loff[n])), bcol(std::max<int64_t>(1, uoff[n]));
+    std::vector<double2> aval(std::max<int64_t>(1, loff[n])), bval(std::max<int64_t>(1, uoff[n]));
+    OM_HIP(hipMemcpyAsync(acol.data(), D.l_col.p, loff[n] * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    OM_HIP(hipMemcpyAsync(aval.data(), D.l_val.p, loff[n] * sizeof(double2), hipMemcpyDeviceToHost, s));
+    OM_HIP(hipMemcpyAsync(bcol.data(), D.u_col.p, uoff[n] * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    OM_HIP(hipMemcpyAsync(bval.data(), D.u_val.p, uoff[n] * sizeof(double2), hipMemcpyDeviceToHost, s));
     OM_HIP(hipStreamSynchronize(s));
     F->n = n;
     F->l_ptr.assign(n + 1, 0);
@@ -693,7 +762,7 @@ om_status ilut_factor_gpu(const om_csr* A, int item, double drop_tol, double fil
     }
     F->perm.resize(n);
     for (int64_t r = 0; r < n; ++r) F->perm[r] = (int32_t)r;
-    F->repaired = hs[3];
+    F->repaired = D.repaired;
     F->pivots = 0;
     return OM_OK;
 }

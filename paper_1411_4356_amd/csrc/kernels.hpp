@@ -29,9 +29,6 @@ om_status residual(const om_csr* A, int adjoint, const VT* b, const VT* x, VT* r
                    const int32_t* active, hipStream_t s, const int32_t* act_host = nullptr);
 double spmv_bytes(const om_csr* A, size_t s, const int32_t* act_host);
 
-// ilut_gpu.hip: device ILUT of batch item `item` of A (factor returned on the host)
-om_status ilut_factor_gpu(const om_csr* A, int item, double drop_tol, double fill_factor, HostFactor* F,
-                          std::string* err, hipStream_t s);
 
 // trsv.hip
 // act_host (nullable): host copy of the active mask, used for byte accounting

@@ -274,6 +274,10 @@ __global__ __launch_bounds__(64 * TW) void trsv_coop_kernel(const TriView<VT>* _
         // ---- helper: far parts of blocks role-1, role-1+H, ...
         int64_t known = 0;   // blocks finished in this epoch, as last observed
         for (int64_t g = role - 1; g < S.nblk; g += a.helpers) {
+            {
+                const int64_t v = rfl64(__hip_atomic_load(progress, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) - ep;
+                if (v > known && v <= S.nblk) known = v;
+            }
             VT acc = czero<VT>();
             bool ok = true;
             const int64_t s1 = S.far_off[g + 1];
@@ -453,6 +457,254 @@ __global__ __launch_bounds__(64 * TW) void trsv_coop_kernel(const TriView<VT>* _
     }
 }
 
+// ---------------------------------------------------------------- several right-hand sides, one factor
+// With one factor shared by the batch, all right-hand sides are solved in one
+// pass over the factor.  The critical workgroup has one wave per right-hand
+// side: per 64-row block every wave takes its side's far+mid partial sums
+// from the helpers, subtracts the near part (block g-1, its side's unknowns
+// in an LDS ring, the near list staged in LDS) and sweeps the diagonal block.
+// The helpers stream the far and mid lists for all sides at once: the
+// unknowns are kept in solve order and interleaved by side (X[c * nb + b]),
+// so that one gathered column is one contiguous run.  Flags and placement of
+// the protocol are those of the single-side kernel above.
+constexpr int MAXB = 8;
+constexpr int MT = 64 * MAXB;
+
+struct MrhsArgs {
+    void* X;               // n * nb of VT
+    void* far_buf;         // nblk * nb * 64 of VT
+    int32_t* fdone;
+    int64_t* progress;
+    int32_t* abort_flag;
+    uint32_t epoch;
+    int helpers;
+    int nb;
+    unsigned long long* tstat;   // diagnostics (nullable): wall-clock ticks waiting / total
+};
+
+template <typename VT>
+struct MrhsShared {
+    union {
+        struct {
+            VT tri[2][TRI_N];
+            VT near_v[NEAR_PF][64];
+            uint8_t near_c[NEAR_PF][64];   // column within the previous block
+            VT ring[RING][MAXB];
+        } cw;
+        struct {
+            VT part[MAXB][MAXB][64];       // [wave][side][lane]
+        } hp;
+    };
+    int fail;
+    int orbuf[MAXB];
+};
+
+template <typename VT>
+__device__ inline int mrhs_block_or(bool v, int* buf) {
+    const unsigned long long b = __ballot(v);
+    if ((threadIdx.x & 63) == 0) buf[threadIdx.x >> 6] = b != 0ull;
+    __syncthreads();
+    int r = 0;
+    for (int w = 0; w < MAXB; ++w) r |= buf[w];
+    __syncthreads();
+    return __builtin_amdgcn_readfirstlane(r);
+}
+
+template <typename VT>
+__global__ __launch_bounds__(MT) void trsv_mrhs_kernel(const TriView<VT>* __restrict__ views, int kind,
+                                                        const VT* rhs, VT* out, int64_t n,
+                                                        const int32_t* __restrict__ active, MrhsArgs a) {
+    const TriView<VT> S = views[kind];
+    const int role = blockIdx.x;
+    if (role > a.helpers) return;
+    const int nb = a.nb;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    VT* X = reinterpret_cast<VT*>(a.X);
+    VT* far_buf = reinterpret_cast<VT*>(a.far_buf);
+    const int64_t ep = (int64_t)a.epoch << 32;
+    __shared__ MrhsShared<VT> sh;
+
+    if (role > 0) {
+        // ---- helper: far and mid parts of blocks role-1, role-1+H, ... for all sides
+        int64_t known = 0;
+        for (int64_t g = role - 1; g < S.nblk; g += a.helpers) {
+            // blocks finished so far.  Every time more are seen finished, an acquire
+            // fence drops cached lines, so that the unknowns of finished blocks can
+            // be read with plain (wide) loads
+            {
+                const int64_t v = rfl64(__hip_atomic_load(a.progress, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) - ep;
+                if (v > known && v <= S.nblk) {
+                    known = v;
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                }
+            }
+            VT acc[MAXB];
+#pragma unroll
+            for (int b = 0; b < MAXB; ++b) acc[b] = czero<VT>();
+            bool ok = true;
+            for (int list = 0; list < 2 && ok; ++list) {
+                const int64_t* off = list == 0 ? S.far_off : S.mid_off;
+                const int32_t* cl = list == 0 ? S.far_col : S.mid_col;
+                const VT* vl = list == 0 ? S.far_val : S.mid_val;
+                const int64_t s1 = off[g + 1];
+                for (int64_t c0 = off[g] + (int64_t)wave * 2; c0 < s1; c0 += (int64_t)MAXB * 2) {
+                    const int cnt = (int)(s1 - c0 < 2 ? s1 - c0 : 2);
+                    // newest block read by the chunk: far slots carry it, mid slots read block g-2
+                    int64_t needmax = 0;
+                    if (list == 0) {
+                        for (int j = 0; j < cnt; ++j)
+                            needmax = needmax > S.far_need[c0 + j] ? needmax : (int64_t)S.far_need[c0 + j];
+                    } else {
+                        needmax = g - 2;
+                    }
+                    if (needmax + 1 > known) {
+                        const int64_t v = rfl64(wait_ge64(a.progress, ep + needmax + 1, a.abort_flag));
+                        if (v < 0) { ok = false; break; }
+                        known = v - ep;
+                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                    }
+                    int32_t cc[2];
+                    VT vv[2];
+#pragma unroll
+                    for (int j = 0; j < 2; ++j)
+                        if (j < cnt) {
+                            cc[j] = cl[(c0 + j) * 64 + lane];
+                            vv[j] = vl[(c0 + j) * 64 + lane];
+                        }
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) {
+                        if (j >= cnt) continue;
+                        const int64_t c = cc[j];
+                        const VT* px = X + c * nb;
+                        VT xv[MAXB];
+#pragma unroll
+                        for (int b = 0; b < MAXB; ++b)
+                            if (b < nb) xv[b] = px[b];
+#pragma unroll
+                        for (int b = 0; b < MAXB; ++b)
+                            if (b < nb) cfma(acc[b], vv[j], xv[b]);
+                    }
+                }
+            }
+#pragma unroll
+            for (int b = 0; b < MAXB; ++b) sh.hp.part[wave][b][lane] = acc[b];
+            if (mrhs_block_or<VT>(!ok, sh.orbuf)) return;
+            // wave w < nb sums side w over the waves
+            if (wave < nb) {
+                VT t = sh.hp.part[0][wave][lane];
+#pragma unroll
+                for (int w = 1; w < MAXB; ++w) t = cadd(t, sh.hp.part[w][wave][lane]);
+                st_wt(far_buf + (g * nb + wave) * 64 + lane, t);
+            }
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+            if (threadIdx.x == 0) __hip_atomic_store(a.fdone + g, (int32_t)a.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        return;
+    }
+
+    // ---- critical workgroup: wave w solves side w
+    const bool mine = wave < nb;
+    const bool act = mine && (!active || active[wave]);
+    const VT* y = rhs + (int64_t)(mine ? wave : 0) * n;
+    VT* x = out + (int64_t)(mine ? wave : 0) * n;
+    constexpr int TPER = (TRI_N + MT - 1) / MT;
+    constexpr int NPER = (NEAR_PF * 64 + MT - 1) / MT;
+    static_assert(TPER == 4 && NPER == 8, "register staging is written out for 4 + 8 entries per thread");
+    // registers: the next block's triangle and near list (named, so that they
+    // stay in registers across the loop)
+    VT tv0, tv1, tv2, tv3;
+    VT nv0, nv1, nv2, nv3, nv4, nv5, nv6, nv7;
+    int32_t nc0 = 0, nc1 = 0, nc2 = 0, nc3 = 0, nc4 = 0, nc5 = 0, nc6 = 0, nc7 = 0;
+#define MRHS_FT(j) { const int t = threadIdx.x + (j) * MT; if (t < TRI_N) tv##j = S.dg[gb * TRI_N + t]; }
+#define MRHS_FN(j) { const int t = threadIdx.x + (j) * MT; const int64_t sl = n0 + t / 64; \
+                     if (sl < n1) { nc##j = S.near_col[sl * 64 + (t & 63)]; nv##j = S.near_val[sl * 64 + (t & 63)]; } }
+#define MRHS_ST(j) { const int t = threadIdx.x + (j) * MT; if (t < TRI_N) sh.cw.tri[buf][t] = tv##j; }
+#define MRHS_SN(j) { const int t = threadIdx.x + (j) * MT; if (n0 + t / 64 < n1) { \
+                     sh.cw.near_c[t / 64][t & 63] = (uint8_t)(nc##j & 63); sh.cw.near_v[t / 64][t & 63] = nv##j; } }
+#define MRHS_FETCH(GB) { const int64_t gb = (GB); \
+        MRHS_FT(0) MRHS_FT(1) MRHS_FT(2) MRHS_FT(3) \
+        const int64_t n0 = S.near_off[gb], n1 = S.near_off[gb + 1]; \
+        MRHS_FN(0) MRHS_FN(1) MRHS_FN(2) MRHS_FN(3) MRHS_FN(4) MRHS_FN(5) MRHS_FN(6) MRHS_FN(7) }
+    tv0 = tv1 = tv2 = tv3 = czero<VT>();
+    nv0 = nv1 = nv2 = nv3 = nv4 = nv5 = nv6 = nv7 = czero<VT>();
+    if (threadIdx.x == 0) {
+        sh.fail = 0;
+        __hip_atomic_store(a.progress, ep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    unsigned long long t_wait = 0, t_all = 0;
+    if (a.tstat && threadIdx.x == 0) t_all = wall_clock64();
+    // right-hand side (with the pivot scaling) of the next block, prefetched
+    VT yn = czero<VT>(), dn = czero<VT>();
+#define MRHS_FETCH_Y(GB) if (mine) { const int64_t rw = (GB) * 64 + lane; \
+        if (rw < n) { yn = y[S.rev ? (n - 1 - rw) : rw]; if (S.dinv) dn = S.dinv[rw]; } }
+    MRHS_FETCH(0)
+    MRHS_FETCH_Y(0)
+    for (int64_t g = 0; g < S.nblk; ++g) {
+        const int buf = (int)(g & 1);
+        {   // stage block g from the registers into LDS
+            MRHS_ST(0) MRHS_ST(1) MRHS_ST(2) MRHS_ST(3)
+            const int64_t n0 = S.near_off[g], n1 = S.near_off[g + 1];
+            MRHS_SN(0) MRHS_SN(1) MRHS_SN(2) MRHS_SN(3) MRHS_SN(4) MRHS_SN(5) MRHS_SN(6) MRHS_SN(7)
+        }
+        __syncthreads();
+        // this block's right-hand side, then the next block's loads in flight
+        const int64_t row = g * 64 + lane;
+        const bool valid = row < n;
+        const int64_t mi = S.rev ? (n - 1 - row) : row;
+        VT r = czero<VT>();
+        if (mine && valid) r = S.dinv ? cmul(yn, dn) : yn;
+        if (g + 1 < S.nblk) {
+            MRHS_FETCH(g + 1)
+            MRHS_FETCH_Y(g + 1)
+        }
+        // near part (block g-1, from the ring) while the helpers finish block g
+        if (mine) {
+            const int64_t n0 = S.near_off[g], n1 = S.near_off[g + 1];
+            const int64_t nl = n1 - n0 < NEAR_PF ? n1 - n0 : NEAR_PF;
+            const int base = (int)(((g - 1) * 64) & (RING - 1));
+            VT acc = czero<VT>();
+            for (int64_t k = 0; k < nl; ++k)
+                cfma(acc, sh.cw.near_v[k][lane], sh.cw.ring[(base + sh.cw.near_c[k][lane]) & (RING - 1)][wave]);
+            // rows with more near entries than staged: the rest from memory
+            for (int64_t k = n0 + NEAR_PF; k < n1; ++k) {
+                const int32_t c = S.near_col[k * 64 + lane];
+                cfma(acc, S.near_val[k * 64 + lane], sh.cw.ring[c & (RING - 1)][wave]);
+            }
+            r = csub(r, acc);
+        }
+        unsigned long long tw0 = 0;
+        if (a.tstat && threadIdx.x == 0) tw0 = wall_clock64();
+        if (threadIdx.x == 0 && !wait_eq32(a.fdone + g, (int32_t)a.epoch, a.abort_flag)) sh.fail = 1;
+        if (a.tstat && threadIdx.x == 0) t_wait += wall_clock64() - tw0;
+        __syncthreads();
+        if (__builtin_amdgcn_readfirstlane(sh.fail)) return;
+        if (mine) {
+            r = csub(r, ld_coh(far_buf + (g * nb + wave) * 64 + lane));
+            r = sweep(r, sh.cw.tri[buf], lane);
+            sh.cw.ring[(g * 64 + lane) & (RING - 1)][wave] = r;
+            if (valid) {
+                st_wt(X + row * nb + wave, r);
+                if (act) x[mi] = r;
+            }
+        }
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (threadIdx.x == 0) __hip_atomic_store(a.progress, ep + g + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (a.tstat && threadIdx.x == 0) {
+        a.tstat[0] = t_wait;
+        a.tstat[1] = wall_clock64() - t_all;
+    }
+}
+#undef MRHS_FT
+#undef MRHS_FN
+#undef MRHS_ST
+#undef MRHS_SN
+#undef MRHS_FETCH
+#undef MRHS_FETCH_Y
+
 // ---------------------------------------------------------------- launch
 
 // Algorithmic bytes of one triangular solve over the active items: values and
@@ -473,9 +725,85 @@ static bool use_chain() {
     return e && e[0] == 'c' && e[1] == 'h';   // "chain" forces the single-workgroup kernel
 }
 
+// Several right-hand sides with the shared factor of M: the factor is read
+// once per solve.  Returns OM_EINVAL (nothing launched) when it does not apply.
+template <typename VT>
+static om_status launch_mrhs(om_ilu* M, const TriView<VT>* views, int kind, const VT* rhs, VT* out,
+                             const int32_t* active, const int32_t* act_host, hipStream_t s) {
+    const int B = M->batch;
+    if (!M->shared || B < 2 || B > MAXB || use_chain()) return OM_EINVAL;
+    // opt-in (OMSS_TRSV_MRHS=1): one critical path for all sides is slower than
+    // one per side on separate CUs while the solve is latency-bound
+    const char* me = getenv("OMSS_TRSV_MRHS");
+    if (!me || me[0] != '1') return OM_EINVAL;
+    static int maxgrid[2] = {0, 0};
+    int& mg = maxgrid[sizeof(VT) == sizeof(double2)];
+    if (mg == 0) {
+        int dev = 0, cus = 0, per = 0, coop = 0;
+        OM_HIP(hipGetDevice(&dev));
+        OM_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        OM_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
+        OM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, trsv_mrhs_kernel<VT>, MT, 0));
+        mg = coop && per > 0 ? cus * per : -1;
+    }
+    if (mg < 2) return OM_EINVAL;
+    const TriSched& T = M->sched[kind];
+    const int64_t n = M->n, nblk = T.nblk;
+    TrsvScratch& X = M->scratch;
+    if (X.m_x.n < (size_t)n * B || X.m_far.n < (size_t)nblk * B * 64 || X.m_fdone.n < (size_t)nblk) {
+        OM_TRY(X.m_x.alloc((size_t)n * B));
+        OM_TRY(X.m_far.alloc((size_t)nblk * B * 64));
+        OM_TRY(X.m_fdone.alloc((size_t)nblk));
+        OM_TRY(X.m_progress.alloc(1));
+        OM_HIP(hipMemsetAsync(X.m_fdone.p, 0, X.m_fdone.bytes(), s));
+        OM_HIP(hipMemsetAsync(X.m_progress.p, 0, X.m_progress.bytes(), s));
+        OM_HIP(hipStreamSynchronize(s));
+    }
+    int H = (int)std::min<int64_t>(mg - 1, nblk);
+    if (const char* e = getenv("OMSS_TRSV_HELPERS")) H = std::max(1, std::min(H, atoi(e)));
+    MrhsArgs a;
+    a.X = X.m_x.p;
+    a.far_buf = X.m_far.p;
+    a.fdone = X.m_fdone.p;
+    a.progress = X.m_progress.p;
+    a.abort_flag = X.abort_flag.p;
+    a.epoch = ++X.epoch;
+    if (a.epoch == 0) a.epoch = ++X.epoch;
+    a.helpers = H;
+    a.nb = B;
+    static unsigned long long* tst = nullptr;
+    a.tstat = nullptr;
+    if (getenv("OMSS_TRSV_STATS")) {
+        if (!tst) OM_HIP(hipMalloc((void**)&tst, 2 * sizeof(unsigned long long)));
+        a.tstat = tst;
+    }
+    int nact = B;
+    if (act_host) {
+        nact = 0;
+        for (int i = 0; i < B; ++i) nact += act_host[i] != 0;
+    }
+    const double bytes = (double)T.nnz * (double)(sizeof(VT) + 4) +
+                         (double)nact * (2.0 * (double)n * sizeof(VT) + (T.has_dinv ? (double)n * sizeof(VT) : 0.0));
+    ProfScope prof("trsv", s, profile_enabled() ? bytes : 0.0);
+    void* args[] = {(void*)&views, (void*)&kind, (void*)&rhs, (void*)&out, (void*)&n, (void*)&active, (void*)&a};
+    OM_HIP(hipLaunchCooperativeKernel((const void*)trsv_mrhs_kernel<VT>, dim3(1 + H), dim3(MT), args, 0, s));
+    if (a.tstat) {
+        unsigned long long h[2];
+        OM_HIP(hipMemcpyAsync(h, a.tstat, sizeof h, hipMemcpyDeviceToHost, s));
+        OM_HIP(hipStreamSynchronize(s));
+        fprintf(stderr, "[trsv stats] multi-side kind %d, %d sides, H=%d: %lld blocks, critical workgroup %.3f ms, "
+                "of which waiting for helpers %.3f ms\n", kind, B, H, (long long)nblk, h[1] / 1e5, h[0] / 1e5);
+    }
+    return OM_OK;
+}
+
 template <typename VT>
 static om_status launch_trsv(om_ilu* M, const TriView<VT>* views, int kind, const VT* rhs, VT* out,
                              const int32_t* active, const int32_t* act_host, hipStream_t s) {
+    {
+        const om_status r = launch_mrhs<VT>(M, views, kind, rhs, out, active, act_host, s);
+        if (r != OM_EINVAL) return r;
+    }
     ProfScope prof("trsv", s, profile_enabled() ? trsv_bytes(M, kind, sizeof(VT), act_host) : 0.0);
     const int B = M->batch;
     if (!use_chain()) {

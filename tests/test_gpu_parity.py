@@ -341,3 +341,55 @@ def test_autograd_steady_state_obs_matches_oracle_adjoint():
     assert np.max(np.abs(obs.detach().numpy() - vals) / np.abs(vals)) <= 1e-10
     ref = wts.numpy() @ go
     assert np.max(np.abs(theta.grad.numpy() - ref)) <= 1e-7 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("ci", [1, 3])
+def test_device_built_schedules_equal_host_built(ci, monkeypatch):
+    """The L and U solve schedules built on the device from the device factor
+    are the host-built ones: both preconditioner applications give the same
+    bits, in complex128 and complex64, forward and adjoint."""
+    p, d, fill = ILUT_CASES[ci]
+    A, _ = P.liouvillian_build([p, p.replace(E=0.3)])
+    B, perm, _ = P.rcm_permute(A)
+    monkeypatch.delenv("OMSS_ILU_SCHED", raising=False)
+    Md = P.ilu_factor(B, d, fill, c64=True, adjoint=True)
+    monkeypatch.setenv("OMSS_ILU_SCHED", "host")
+    Mh = P.ilu_factor(B, d, fill, c64=True, adjoint=True)
+    X = W.random_complex(B.n, seed=11, count=2)
+    for dt in (torch.complex128, torch.complex64):
+        for adj in (False, True):
+            yd = to_host(P.ilu_apply(Md, to_dev(X, dt), adjoint=adj))
+            yh = to_host(P.ilu_apply(Mh, to_dev(X, dt), adjoint=adj))
+            assert np.array_equal(yd.view(np.uint64 if dt == torch.complex128 else np.uint32),
+                                  yh.view(np.uint64 if dt == torch.complex128 else np.uint32))
+
+
+@pytest.mark.parametrize("nb", [2, 3, 8])
+def test_multi_rhs_solve_with_shared_factor(nb, monkeypatch):
+    """With one factor shared by the batch, the triangular solves of all
+    right-hand sides run as one pass over the factor; results agree with the
+    one-side-at-a-time solves (summation order differs) in both precisions and
+    directions, and the factor's own host application."""
+    ps = [W.BATCH_BASE.replace(nc=4, nm=9, E=0.2 + 0.05 * b) for b in range(nb)]
+    A, _ = P.liouvillian_build(ps)
+    B, perm, _ = P.rcm_permute(A)
+    M = P.ilu_factor(B, 1e-6, 60.0, shared=True, c64=True, adjoint=True, keep_host=True)
+    L0, U0 = M.export(0)
+    X = W.random_complex(B.n, seed=21, count=nb)
+    for dt, tol in ((torch.complex128, 1e-12), (torch.complex64, 2e-4)):
+        for adj in (False, True):
+            monkeypatch.setenv("OMSS_TRSV_MRHS", "1")
+            ym = to_host(P.ilu_apply(M, to_dev(X, dt), adjoint=adj))
+            monkeypatch.setenv("OMSS_TRSV_MRHS", "0")
+            ys = to_host(P.ilu_apply(M, to_dev(X, dt), adjoint=adj))
+            for b in range(nb):
+                ref = oilut.apply(L0, U0, X[b], adjoint=adj)
+                assert np.linalg.norm(ym[b] - ys[b]) <= tol * np.linalg.norm(ys[b])
+                assert np.linalg.norm(ym[b] - ref) <= tol * np.linalg.norm(ref)
+    # in place, and with items masked out by a converged solve: steady states
+    monkeypatch.setenv("OMSS_TRSV_MRHS", "1")
+    rho, info, res = P.steady_state(ps, drop_tol=1e-6, fill_factor=60.0, m=60, tol=1e-11, share_factor=True)
+    rho = to_host(rho)
+    for b, p in enumerate(ps):
+        ro, _ = direct.steady_state(p)
+        assert np.max(np.abs(rho[b] - ro)) <= 1e-8
