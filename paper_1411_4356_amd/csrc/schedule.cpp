@@ -12,8 +12,13 @@
 // that lie left of it are stored slot-major (ELL) in three lists by the block
 // of their column: "near" (block g-1), "mid" (block g-2) and "far" (older);
 // slot s of row r of block g is at [(off[g] + s) * 64 + r], columns
-// increasing with s, short rows padded with value 0.  For every far slot,
-// need[slot] is the newest column block it reads.  The strictly-lower part of
+// increasing with s, short rows padded with value 0.  Near and mid rows start
+// at slot 0 and are padded at the end; far rows end at the last slot and are
+// padded at the start, so that the far slots read older blocks first and the
+// slots that need the newest blocks are few (each far slot takes the newest
+// block of its 64 rows, and a row padded at the end would reach its own
+// newest columns early).  For every far slot, need[slot] is the newest
+// column block it reads.  The strictly-lower part of
 // the 64x64 diagonal block is stored dense and packed by column.
 #include <algorithm>
 #include <cmath>
@@ -96,7 +101,9 @@ void build_host_tri(const SolveCSR& T, HostTri& H) {
         }
         for (int r = 0; r < BLK && r0 + r < n; ++r) {
             const int64_t i = r0 + r;
-            int64_t sl[3] = {0, 0, 0};
+            int64_t nfar = 0;
+            for (int64_t t = T.ptr[i]; t < T.ptr[i + 1]; ++t) nfar += cls(T.col[t], g) == 0;
+            int64_t sl[3] = {H.far_off[g + 1] - H.far_off[g] - nfar, 0, 0};
             for (int64_t t = T.ptr[i]; t < T.ptr[i + 1]; ++t) {
                 const int64_t c = T.col[t];
                 const int k = cls(c, g);

@@ -2,7 +2,8 @@
 // (the factor stays in HBM).  Same layout as the host build (schedule.cpp):
 // per 64-row block the entries left of the block in three slot-major lists
 // (far: column block <= g-3, mid: g-2, near: g-1; columns increasing with the
-// slot, short rows padded with value 0 and a column of a finished block),
+// slot, short rows padded with value 0 and a column of a finished block, far
+// rows aligned to the last slot and the others to the first),
 // need[slot] = newest column block a far slot reads, and the strictly-lower
 // 64x64 diagonal block packed by column.
 //   kind 0: L as stored (unit lower, no scaling);
@@ -145,9 +146,13 @@ __global__ __launch_bounds__(BLK) void tri_fill_kernel(RowSrc F, int64_t n, TriO
     const int64_t g = blockIdx.x;
     const int r = threadIdx.x;
     const int64_t ip = g * BLK + r;
-    int64_t idx[3] = {0, 0, 0};
+    const int64_t nf = o.off[0][g + 1] - o.off[0][g];
+    int64_t idx[3] = {0, 0, 0};   // next slot per list; far: starts past the padding
+    int64_t fpad = nf;            // far slots of padding (all when the row is past n)
     if (ip < n) {
         const SolveRow<KIND> R(F, n, ip);
+        fpad = nf - R.below(n, (g - 2) * BLK);
+        idx[0] = fpad;
         for (int64_t q = 0; q < R.len; ++q) {
             int64_t c;
             double2 v;
@@ -171,11 +176,13 @@ __global__ __launch_bounds__(BLK) void tri_fill_kernel(RowSrc F, int64_t n, TriO
             if (o.dinv32) o.dinv32[ip] = make_float2((float)d.x, (float)d.y);
         }
     }
-    // padding: value 0, a column of a finished block (far: column 0)
+    // padding: value 0, a column of a finished block (far: column 0, before
+    // the row's entries; mid and near: after them)
     for (int k = 0; k < 3; ++k) {
-        const int64_t s1 = o.off[k][g + 1] - o.off[k][g];
+        const int64_t s0 = k == 0 ? 0 : idx[k];
+        const int64_t s1 = k == 0 ? fpad : o.off[k][g + 1] - o.off[k][g];
         const int32_t pad = k == 0 ? 0 : (int32_t)((g - 3 + k) * BLK > 0 ? (g - 3 + k) * BLK : 0);
-        for (int64_t s = idx[k]; s < s1; ++s) {
+        for (int64_t s = s0; s < s1; ++s) {
             const int64_t at = (o.off[k][g] + s) * BLK + r;
             o.col[k][at] = pad;
             o.val[k][at] = make_double2(0.0, 0.0);
@@ -183,9 +190,9 @@ __global__ __launch_bounds__(BLK) void tri_fill_kernel(RowSrc F, int64_t n, TriO
         }
     }
     // far_need: the newest column block any lane reads in the slot
-    const int64_t f0 = o.off[0][g], nf = o.off[0][g + 1] - f0;
+    const int64_t f0 = o.off[0][g];
     for (int64_t s = 0; s < nf; ++s) {
-        int64_t need = s < idx[0] ? (int64_t)o.col[0][(f0 + s) * BLK + r] / BLK : 0;
+        int64_t need = s >= fpad ? (int64_t)o.col[0][(f0 + s) * BLK + r] / BLK : 0;
         need = wave_max(need);
         if (r == 0) o.far_need[f0 + s] = (int32_t)need;
     }

@@ -52,25 +52,57 @@ constexpr int RING = NEAR_BLOCKS * 64;
 constexpr int NEAR_PF = 64;        // near slots of the next block staged in LDS (all: a row has at most 64 entries in the previous block)
 constexpr int NXCD = 8;
 constexpr int FU = 8;               // slots per wave per chunk in the streamed loops
+constexpr int FH = 16;              // the same for the far lists streamed by the helpers
 constexpr long long SPIN_LIMIT = 1ll << 22;
 
 // Column sweep of the unit-lower diagonal block (wave 0): r holds the right-
-// hand side of lane = row on entry and the unknown on exit.
+// hand side of lane = row on entry and the unknown on exit.  Columns are
+// taken in chunks of SWC: the LDS entries of chunk k+1 are requested before
+// the steps of chunk k (scheduling barriers keep that order), so that the
+// chain of dependent steps does not wait for LDS.
+constexpr int SWC = 8;
 template <typename VT>
-__device__ inline VT sweep(VT r, const VT* tri, int lane) {
+__device__ __forceinline__ void sweep_load(VT (&t)[SWC], const VT* tri, int c0, int lane) {
+#pragma unroll
+    for (int j = 0; j < SWC; ++j) {
+        const int c = c0 + j;
+        if (c < 63) t[j] = tri[c * 63 - (c * (c - 1)) / 2 + (lane > c ? lane - c - 1 : 0)];
+    }
+}
+template <int K, typename VT>
+__device__ __forceinline__ void sweep_chunk(VT& r, const VT (&cur)[SWC], VT (&nxt)[SWC], const VT* tri, int lane) {
     using ST = typename Scalar<VT>::type;
-#pragma unroll 9
-    for (int c = 0; c < 63; ++c) {
-        const VT t = tri[c * 63 - (c * (c - 1)) / 2 + (lane > c ? lane - c - 1 : 0)];
-        const ST xr = bcast(r.x, c);
-        const ST xi = bcast(r.y, c);
-        if (lane > c) {
-            r.x -= t.x * xr;
-            r.x += t.y * xi;
-            r.y -= t.x * xi;
-            r.y -= t.y * xr;
+    if (K + 1 < 8) sweep_load(nxt, tri, (K + 1) * SWC, lane);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int j = 0; j < SWC; ++j) {
+        const int c = K * SWC + j;
+        if (c < 63) {
+            const VT t = cur[j];
+            const ST xr = bcast(r.x, c);
+            const ST xi = bcast(r.y, c);
+            if (lane > c) {
+                r.x -= t.x * xr;
+                r.x += t.y * xi;
+                r.y -= t.x * xi;
+                r.y -= t.y * xr;
+            }
         }
     }
+    __builtin_amdgcn_sched_barrier(0);
+}
+template <typename VT>
+__device__ __forceinline__ VT sweep(VT r, const VT* tri, int lane) {
+    VT ta[SWC], tb[SWC];
+    sweep_load(ta, tri, 0, lane);
+    sweep_chunk<0>(r, ta, tb, tri, lane);
+    sweep_chunk<1>(r, tb, ta, tri, lane);
+    sweep_chunk<2>(r, ta, tb, tri, lane);
+    sweep_chunk<3>(r, tb, ta, tri, lane);
+    sweep_chunk<4>(r, ta, tb, tri, lane);
+    sweep_chunk<5>(r, tb, ta, tri, lane);
+    sweep_chunk<6>(r, ta, tb, tri, lane);
+    sweep_chunk<7>(r, tb, ta, tri, lane);
     return r;
 }
 
@@ -230,17 +262,42 @@ __device__ inline bool wait_eq32(const int32_t* p, int32_t v, int32_t* abort_fla
     return true;
 }
 
-template <typename VT>
-struct CoopShared {
-    VT tri[2][TRI_N];
-    VT near_v[NEAR_PF][64];
-    int32_t near_c[NEAR_PF][64];
-    VT part[TW][64];
-    VT mid[2][TW - 1][64];
-    VT ring[RING];
-    int fail;
-    int orbuf[TW];
-};
+// Loads through explicit address spaces: read-only schedule metadata with a
+// wave-uniform index through the scalar cache (its wait does not include the
+// vector loads in flight), everything else as global (not flat) loads.
+template <typename T>
+__device__ __forceinline__ T ldc(const T* p) { return *(const __attribute__((address_space(4))) T*)p; }
+template <typename T>
+__device__ __forceinline__ T ldg(const T* p) { return *(const __attribute__((address_space(1))) T*)p; }
+// complex values through the compiler's own vector types (a load of the HIP
+// vector class would go through its generic-pointer copy constructor)
+template <>
+__device__ __forceinline__ double2 ldg<double2>(const double2* p) {
+    typedef double v2 __attribute__((ext_vector_type(2)));
+    const v2 v = *(const __attribute__((address_space(1))) v2*)p;
+    return make_double2(v.x, v.y);
+}
+template <>
+__device__ __forceinline__ float2 ldg<float2>(const float2* p) {
+    typedef float v2 __attribute__((ext_vector_type(2)));
+    const v2 v = *(const __attribute__((address_space(1))) v2*)p;
+    return make_float2(v.x, v.y);
+}
+
+// Copy `bytes` (a multiple of 16) from global memory to LDS without passing
+// through registers: 1 KiB per wave instruction (16 bytes per lane), chunks
+// dealt to the `nw` waves numbered from `w`.  The copy completes
+// asynchronously; the caller waits (s_waitcnt) before its next barrier.
+__device__ inline void copy_to_lds(void* dst, const void* src, int64_t bytes, int w, int nw, int lane) {
+    const char* sp = static_cast<const char*>(src);
+    char* dp = static_cast<char*>(dst);
+    for (int64_t c = (int64_t)w * 1024; c < bytes; c += (int64_t)nw * 1024) {
+        const int64_t off = c + (int64_t)lane * 16;
+        if (off < bytes)
+            __builtin_amdgcn_global_load_lds(sp + off, (__attribute__((address_space(3))) void*)(dp + c), 16, 0, 0);
+    }
+}
+
 
 template <typename VT>
 __global__ __launch_bounds__(64 * TW) void trsv_coop_kernel(const TriView<VT>* __restrict__ views, int kind,
@@ -268,7 +325,16 @@ __global__ __launch_bounds__(64 * TW) void trsv_coop_kernel(const TriView<VT>* _
     int32_t* fdone = a.fdone + (int64_t)b * S.nblk;
     int64_t* progress = a.progress + b;
     const int64_t ep = (int64_t)a.epoch << 32;
-    __shared__ CoopShared<VT> sh;
+    // LDS of the critical workgroup, as separate objects: the compiler then
+    // knows that reads of one do not depend on copies still landing in another
+    __shared__ __attribute__((aligned(16))) VT s_tri[2][TRI_N];
+    __shared__ __attribute__((aligned(16))) VT s_near_v[NEAR_PF][64];
+    __shared__ __attribute__((aligned(16))) int32_t s_near_c[NEAR_PF][64];
+    __shared__ VT s_part[TW][64];
+    __shared__ VT s_mid[2][TW - 1][64];
+    __shared__ VT s_ring[RING];
+    __shared__ int s_fail;
+    __shared__ int s_orbuf[TW];
 
     if (role > 0) {
         // ---- helper: far parts of blocks role-1, role-1+H, ...
@@ -280,15 +346,24 @@ __global__ __launch_bounds__(64 * TW) void trsv_coop_kernel(const TriView<VT>* _
             }
             VT acc = czero<VT>();
             bool ok = true;
-            const int64_t s1 = S.far_off[g + 1];
-            // chunks of FU consecutive slots per wave: one progress check per chunk,
-            // all column/value loads of the chunk issued before the gathers
-            for (int64_t c0 = S.far_off[g] + (int64_t)wave * FU; c0 < s1; c0 += (int64_t)TW * FU) {
-                const int cnt = (int)(s1 - c0 < FU ? s1 - c0 : FU);
-                int64_t needmax = 0;
+            const int64_t s1 = ldc(S.far_off + g + 1);
+            // chunks of FH consecutive slots per wave: the columns and values of a
+            // chunk are loaded first (they do not depend on the solve), then the
+            // progress is checked once for the chunk, then the unknowns are gathered
+            for (int64_t c0 = ldc(S.far_off + g) + (int64_t)wave * FH; c0 < s1; c0 += (int64_t)TW * FH) {
+                const int cnt = (int)(s1 - c0 < FH ? s1 - c0 : FH);
+                // slots past the end of the block repeat its last slot (no
+                // branches between the loads) and are not accumulated
+                int32_t cc[FH];
+                VT vv[FH];
 #pragma unroll
-                for (int j = 0; j < FU; ++j)
-                    if (j < cnt) needmax = needmax > S.far_need[c0 + j] ? needmax : (int64_t)S.far_need[c0 + j];
+                for (int j = 0; j < FH; ++j) {
+                    const int64_t sl = c0 + (j < cnt ? j : cnt - 1);
+                    cc[j] = ldg(S.far_col + sl * 64 + lane);
+                    vv[j] = ldg(S.far_val + sl * 64 + lane);
+                }
+                // far slots need non-decreasing blocks (rows end at the last slot)
+                const int64_t needmax = ldc(S.far_need + c0 + cnt - 1);
                 if (needmax + 2 > known) {
                     // every lane waits for the same target; the result is made
                     // wave-uniform so that the loop exits uniformly
@@ -296,34 +371,25 @@ __global__ __launch_bounds__(64 * TW) void trsv_coop_kernel(const TriView<VT>* _
                     if (v < 0) { ok = false; break; }
                     known = v - ep;
                 }
-                int32_t cc[FU];
-                VT vv[FU];
+                VT xv[FH];
 #pragma unroll
-                for (int j = 0; j < FU; ++j)
-                    if (j < cnt) {
-                        cc[j] = S.far_col[(c0 + j) * 64 + lane];
-                        vv[j] = S.far_val[(c0 + j) * 64 + lane];
-                    }
-                VT xv[FU];
+                for (int j = 0; j < FH; ++j) {
+                    const int64_t c = cc[j];
+                    const VT* px = x + (S.rev ? (n - 1 - c) : c);
+                    // unknowns of the newest finished block may share a cache line
+                    // with unfinished rows: read them coherently
+                    xv[j] = (c >> 6) + 1 >= known ? ld_coh(px) : ldg(px);
+                }
 #pragma unroll
-                for (int j = 0; j < FU; ++j)
-                    if (j < cnt) {
-                        const int64_t c = cc[j];
-                        const VT* px = x + (S.rev ? (n - 1 - c) : c);
-                        // unknowns of the newest finished block may share a cache line
-                        // with unfinished rows: read them coherently
-                        xv[j] = (c >> 6) + 1 >= known ? ld_coh(px) : *px;
-                    }
-#pragma unroll
-                for (int j = 0; j < FU; ++j)
+                for (int j = 0; j < FH; ++j)
                     if (j < cnt) cfma(acc, vv[j], xv[j]);
             }
-            sh.part[wave][lane] = acc;
-            if (block_or(!ok, sh.orbuf)) return;
+            s_part[wave][lane] = acc;
+            if (block_or(!ok, s_orbuf)) return;
             if (wave == 0) {
-                VT t = sh.part[0][lane];
+                VT t = s_part[0][lane];
 #pragma unroll
-                for (int w = 1; w < TW; ++w) t = cadd(t, sh.part[w][lane]);
+                for (int w = 1; w < TW; ++w) t = cadd(t, s_part[w][lane]);
                 st_wt(far_buf + g * 64 + lane, t);
                 __builtin_amdgcn_s_waitcnt(0);
                 if (lane == 0) __hip_atomic_store(fdone + g, (int32_t)a.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -335,125 +401,158 @@ __global__ __launch_bounds__(64 * TW) void trsv_coop_kernel(const TriView<VT>* _
 
     // ---- critical workgroup
     const VT* y = rhs + (int64_t)b * n;
-    unsigned long long t_near = 0, t_wait = 0, t_sweep = 0, tA = 0;
+    unsigned long long t_near = 0, t_wait = 0, t_sweep = 0, t_tail = 0, t_pub = 0, t_bar = 0, tA = 0;
     // prologue: triangle and near list of block 0, mid(0) = 0
-    for (int t = threadIdx.x; t < TRI_N; t += 64 * TW) sh.tri[0][t] = S.dg[t];
     {
-        const int64_t n0 = S.near_off[0], n1 = S.near_off[1];
-        for (int64_t s = n0 + wave; s < n1 && s - n0 < NEAR_PF; s += TW) {
-            sh.near_c[s - n0][lane] = S.near_col[s * 64 + lane];
-            sh.near_v[s - n0][lane] = S.near_val[s * 64 + lane];
-        }
+        const int64_t n0 = ldc(S.near_off), n1 = ldc(S.near_off + 1);
+        const int64_t nl = n1 - n0 < NEAR_PF ? n1 - n0 : NEAR_PF;
+        copy_to_lds(s_tri[0], S.dg, (int64_t)TRI_N * sizeof(VT), wave, TW, lane);
+        copy_to_lds(s_near_c, S.near_col + n0 * 64, nl * 64 * 4, wave, TW, lane);
+        copy_to_lds(s_near_v, S.near_val + n0 * 64, nl * 64 * (int64_t)sizeof(VT), wave, TW, lane);
+        __builtin_amdgcn_s_waitcnt(0);
     }
-    if (wave > 0) sh.mid[0][wave - 1][lane] = czero<VT>();
+    if (wave > 0) s_mid[0][wave - 1][lane] = czero<VT>();
     if (threadIdx.x == 0) {
-        sh.fail = 0;
+        s_fail = 0;
         __hip_atomic_store(progress, ep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     __syncthreads();
+    constexpr int MPW = (64 + TW - 2) / (TW - 1);   // mid slots per wave (a row has at most 64)
     for (int64_t g = 0; g < S.nblk; ++g) {
         if (a.tstat && threadIdx.x == 0) tA = wall_clock64();
         const int buf = (int)(g & 1);
+        const int64_t g1 = g + 1;
+        // loads that depend on nothing computed: wave 0 the right-hand side of
+        // block g, waves 1-3 the mid list of block g+1 (columns in block g-1)
+        VT r0 = czero<VT>(), dv = czero<VT>();
+        // (defined on every path, so that they are not live across the sweep)
+        int32_t mc[MPW];
+        VT mv[MPW];
+#pragma unroll
+        for (int j = 0; j < MPW; ++j) { mc[j] = 0; mv[j] = czero<VT>(); }
+        const int64_t m0 = g1 < S.nblk ? ldc(S.mid_off + g1) : 0, m1 = g1 < S.nblk ? ldc(S.mid_off + g1 + 1) : 0;
+        if (wave == 0) {
+            const int64_t row = g * 64 + lane;
+            if (row < n) {
+                r0 = ldg(y + (S.rev ? (n - 1 - row) : row));
+                if (S.dinv) dv = ldg(S.dinv + row);
+            }
+        } else {
+            if (m1 > m0) {
+                // slots past the end repeat the last one (not accumulated)
+#pragma unroll
+                for (int j = 0; j < MPW; ++j) {
+                    int64_t sl = m0 + (wave - 1) + (int64_t)j * (TW - 1);
+                    sl = sl < m1 ? sl : m1 - 1;
+                    mc[j] = ldg(S.mid_col + sl * 64 + lane);
+                    mv[j] = ldg(S.mid_val + sl * 64 + lane);
+                }
+            }
+            // the triangle of block g+1 goes to the idle buffer now
+            if (g1 < S.nblk)
+                copy_to_lds(s_tri[buf ^ 1], S.dg + g1 * TRI_N, (int64_t)TRI_N * sizeof(VT), wave - 1, TW - 1, lane);
+        }
         // near part of block g (columns in block g-1), x from the ring
         VT acc = czero<VT>();
         {
-            const int64_t n0 = S.near_off[g], n1 = S.near_off[g + 1];
+            const int64_t n0 = ldc(S.near_off + g), n1 = ldc(S.near_off + g + 1);
             const int64_t nl = n1 - n0 < NEAR_PF ? n1 - n0 : NEAR_PF;
-            for (int64_t k = wave; k < nl; k += TW) cfma(acc, sh.near_v[k][lane], sh.ring[sh.near_c[k][lane] & (RING - 1)]);
+            // rounds of NR slots per wave: columns, then values and unknowns, then products
+            constexpr int NR = 8;
+            for (int64_t k0 = wave; k0 < nl; k0 += (int64_t)TW * NR) {
+                int32_t cc[NR];
+                VT vv[NR], xv[NR];
+#pragma unroll
+                for (int j = 0; j < NR; ++j)
+                    if (k0 + j * TW < nl) cc[j] = s_near_c[k0 + j * TW][lane];
+#pragma unroll
+                for (int j = 0; j < NR; ++j)
+                    if (k0 + j * TW < nl) { vv[j] = s_near_v[k0 + j * TW][lane]; xv[j] = s_ring[cc[j] & (RING - 1)]; }
+#pragma unroll
+                for (int j = 0; j < NR; ++j)
+                    if (k0 + j * TW < nl) cfma(acc, vv[j], xv[j]);
+            }
             for (int64_t c0 = n0 + NEAR_PF + (int64_t)wave * FU; c0 < n1; c0 += (int64_t)TW * FU) {
                 const int cnt = (int)(n1 - c0 < FU ? n1 - c0 : FU);
                 int32_t cc[FU];
                 VT vv[FU];
 #pragma unroll
                 for (int j = 0; j < FU; ++j)
-                    if (j < cnt) { cc[j] = S.near_col[(c0 + j) * 64 + lane]; vv[j] = S.near_val[(c0 + j) * 64 + lane]; }
+                    if (j < cnt) { cc[j] = ldg(S.near_col + (c0 + j) * 64 + lane); vv[j] = ldg(S.near_val + (c0 + j) * 64 + lane); }
 #pragma unroll
                 for (int j = 0; j < FU; ++j)
-                    if (j < cnt) cfma(acc, vv[j], sh.ring[cc[j] & (RING - 1)]);
+                    if (j < cnt) cfma(acc, vv[j], s_ring[cc[j] & (RING - 1)]);
             }
         }
-        sh.part[wave][lane] = acc;
-        if (wave == 0 && lane == 0) {
-            const unsigned long long tB = a.tstat ? wall_clock64() : 0;
-            if (!wait_eq32(fdone + g, (int32_t)a.epoch, a.abort_flag)) sh.fail = 1;
-            if (a.tstat) { const unsigned long long tC = wall_clock64(); t_near += tB - tA; t_wait += tC - tB; tA = tC; }
+        s_part[wave][lane] = acc;
+        VT fb = czero<VT>();
+        if (wave == 0) {
+            // publish block g-1: its unknowns were stored at the end of the
+            // previous iteration, and waiting for them here rather than there
+            // keeps the store latency off the chain of blocks
+            if (g > 0) {
+                const unsigned long long tP = a.tstat ? wall_clock64() : 0;
+                __builtin_amdgcn_s_waitcnt(0);
+                if (lane == 0) __hip_atomic_store(progress, ep + g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (a.tstat && lane == 0) t_pub += wall_clock64() - tP;
+            }
+            if (lane == 0) {
+                const unsigned long long tB = a.tstat ? wall_clock64() : 0;
+                if (!wait_eq32(fdone + g, (int32_t)a.epoch, a.abort_flag)) s_fail = 1;
+                if (a.tstat) { const unsigned long long tC = wall_clock64(); t_near += tB - tA; t_wait += tC - tB; tA = tC; }
+            }
+            // the helpers' far sum of block g (published before the flag)
+            fb = ld_coh(far_buf + g * 64 + lane);
         }
         __syncthreads();
-        if (__builtin_amdgcn_readfirstlane(sh.fail)) return;
+        if (__builtin_amdgcn_readfirstlane(s_fail)) return;
+        if (a.tstat && threadIdx.x == 0) { const unsigned long long tE = wall_clock64(); t_bar += tE - tA; tA = tE; }
         if (wave == 0) {
             const int64_t row = g * 64 + lane;
             const bool valid = row < n;
-            const int64_t mi = S.rev ? (n - 1 - row) : row;
-            VT r = czero<VT>();
-            if (valid) {
-                r = y[mi];
-                if (S.dinv) r = cmul(r, S.dinv[row]);
-            }
-            r = csub(r, ld_coh(far_buf + g * 64 + lane));
+            VT r = S.dinv ? cmul(r0, dv) : r0;
+            r = csub(r, fb);
 #pragma unroll
-            for (int w = 0; w < TW; ++w) r = csub(r, sh.part[w][lane]);
+            for (int w = 0; w < TW; ++w) r = csub(r, s_part[w][lane]);
 #pragma unroll
-            for (int w = 0; w < TW - 1; ++w) r = csub(r, sh.mid[buf][w][lane]);
-            r = sweep(r, sh.tri[buf], lane);
-            sh.ring[(g * 64 + lane) & (RING - 1)] = r;
-            if (valid) st_wt(x + mi, r);
-            __builtin_amdgcn_s_waitcnt(0);
-            if (lane == 0) __hip_atomic_store(progress, ep + g + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (a.tstat && lane == 0) t_sweep += wall_clock64() - tA;
-        } else if (g + 1 < S.nblk) {
-            // waves 1-3: stage block g+1 and compute its mid part (block g-1, in the ring)
-            const int64_t g1 = g + 1;
-            constexpr int TPER = (TRI_N + 64 * (TW - 1) - 1) / (64 * (TW - 1));
+            for (int w = 0; w < TW - 1; ++w) r = csub(r, s_mid[buf][w][lane]);
+            r = sweep(r, s_tri[buf], lane);
+            s_ring[(g * 64 + lane) & (RING - 1)] = r;
+            if (valid) st_wt(x + (S.rev ? (n - 1 - row) : row), r);
+            if (a.tstat && lane == 0) { const unsigned long long tD = wall_clock64(); t_sweep += tD - tA; tA = tD; }
+        } else if (g1 < S.nblk) {
+            // waves 1-3: stage the near list of block g+1 (copies straight to
+            // LDS, completed before the barrier) and finish its mid part from
+            // the prefetched list and block g-1 in the ring
             {
-                VT tv[TPER];
-#pragma unroll
-                for (int j = 0; j < TPER; ++j) {
-                    const int t = threadIdx.x - 64 + j * 64 * (TW - 1);
-                    if (t < TRI_N) tv[j] = S.dg[g1 * TRI_N + t];
-                }
-#pragma unroll
-                for (int j = 0; j < TPER; ++j) {
-                    const int t = threadIdx.x - 64 + j * 64 * (TW - 1);
-                    if (t < TRI_N) sh.tri[buf ^ 1][t] = tv[j];
-                }
-            }
-            {
-                const int64_t n0 = S.near_off[g1], n1 = S.near_off[g1 + 1];
-                constexpr int NPER = (NEAR_PF + TW - 2) / (TW - 1);
-                int32_t nc[NPER];
-                VT nv[NPER];
-#pragma unroll
-                for (int j = 0; j < NPER; ++j) {
-                    const int64_t s = n0 + (wave - 1) + (int64_t)j * (TW - 1);
-                    if (s < n1 && s - n0 < NEAR_PF) { nc[j] = S.near_col[s * 64 + lane]; nv[j] = S.near_val[s * 64 + lane]; }
-                }
-#pragma unroll
-                for (int j = 0; j < NPER; ++j) {
-                    const int64_t s = n0 + (wave - 1) + (int64_t)j * (TW - 1);
-                    if (s < n1 && s - n0 < NEAR_PF) { sh.near_c[s - n0][lane] = nc[j]; sh.near_v[s - n0][lane] = nv[j]; }
-                }
+                const int64_t n0 = ldc(S.near_off + g1), n1 = ldc(S.near_off + g1 + 1);
+                const int64_t nl = n1 - n0 < NEAR_PF ? n1 - n0 : NEAR_PF;
+                copy_to_lds(s_near_c, S.near_col + n0 * 64, nl * 64 * 4, wave - 1, TW - 1, lane);
+                copy_to_lds(s_near_v, S.near_val + n0 * 64, nl * 64 * (int64_t)sizeof(VT), wave - 1, TW - 1, lane);
             }
             VT m = czero<VT>();
-            const int64_t m0 = S.mid_off[g1], m1 = S.mid_off[g1 + 1];
-            for (int64_t c0 = m0 + (int64_t)(wave - 1) * FU; c0 < m1; c0 += (int64_t)(TW - 1) * FU) {
-                const int cnt = (int)(m1 - c0 < FU ? m1 - c0 : FU);
-                int32_t cc[FU];
-                VT vv[FU];
 #pragma unroll
-                for (int j = 0; j < FU; ++j)
-                    if (j < cnt) { cc[j] = S.mid_col[(c0 + j) * 64 + lane]; vv[j] = S.mid_val[(c0 + j) * 64 + lane]; }
-#pragma unroll
-                for (int j = 0; j < FU; ++j)
-                    if (j < cnt) cfma(m, vv[j], sh.ring[cc[j] & (RING - 1)]);
+            for (int j = 0; j < MPW; ++j) {
+                const int64_t sl = m0 + (wave - 1) + (int64_t)j * (TW - 1);
+                if (sl < m1) cfma(m, mv[j], s_ring[mc[j] & (RING - 1)]);
             }
-            sh.mid[buf ^ 1][wave - 1][lane] = m;
+            s_mid[buf ^ 1][wave - 1][lane] = m;
+            __builtin_amdgcn_s_waitcnt(0);
         }
         __syncthreads();
+        if (a.tstat && threadIdx.x == 0) t_tail += wall_clock64() - tA;
+    }
+    if (wave == 0) {
+        __builtin_amdgcn_s_waitcnt(0);
+        if (lane == 0) __hip_atomic_store(progress, ep + S.nblk, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     if (a.tstat && threadIdx.x == 0) {
-        atomicAdd(a.tstat + 0, t_near);
+        atomicAdd(a.tstat + 0, t_near - t_pub);
         atomicAdd(a.tstat + 1, t_wait);
         atomicAdd(a.tstat + 2, t_sweep);
+        atomicAdd(a.tstat + 3, t_tail);
+        atomicAdd(a.tstat + 4, t_pub);
+        atomicAdd(a.tstat + 5, t_bar);
     }
 }
 
@@ -822,8 +921,10 @@ static om_status launch_trsv(om_ilu* M, const TriView<VT>* views, int kind, cons
         const int span = (B <= NXCD && NXCD % B == 0) ? NXCD / B : 1;   // XCDs per item
         int H = 0, per_xcd = 0;
         if (mg > 0) {
+            // default: every workgroup slot of the device (the helpers are bound
+            // by the latency of their loads, so more of them stream more)
             const char* e = getenv("OMSS_TRSV_HELPERS");
-            H = e ? atoi(e) : 16 * span;
+            H = e ? atoi(e) : (mg / (NXCD * slots)) * span - 1;
             H = (int)std::min<int64_t>(H, nblk);
             // workgroups of an item: 1 + H over `span` XCDs; grid = 8 * per_xcd * slots
             per_xcd = (1 + H + span - 1) / span;
@@ -845,8 +946,8 @@ static om_status launch_trsv(om_ilu* M, const TriView<VT>* views, int kind, cons
             static unsigned long long* tst = nullptr;
             a.tstat = nullptr;
             if (getenv("OMSS_TRSV_STATS")) {
-                if (!tst) OM_HIP(hipMalloc((void**)&tst, 3 * sizeof(unsigned long long)));
-                OM_HIP(hipMemsetAsync(tst, 0, 3 * sizeof(unsigned long long), s));
+                if (!tst) OM_HIP(hipMalloc((void**)&tst, 6 * sizeof(unsigned long long)));
+                OM_HIP(hipMemsetAsync(tst, 0, 6 * sizeof(unsigned long long), s));
                 a.tstat = tst;
             }
             int64_t n = M->n;
@@ -854,11 +955,12 @@ static om_status launch_trsv(om_ilu* M, const TriView<VT>* views, int kind, cons
             const unsigned grid = span > 1 ? (unsigned)(NXCD * per_xcd) : (unsigned)(NXCD * slots * (1 + H));
             OM_HIP(hipLaunchCooperativeKernel((const void*)trsv_coop_kernel<VT>, dim3(grid), dim3(64 * TW), args, 0, s));
             if (a.tstat) {
-                unsigned long long h[3];
+                unsigned long long h[6];
                 OM_HIP(hipMemcpyAsync(h, a.tstat, sizeof h, hipMemcpyDeviceToHost, s));
                 OM_HIP(hipStreamSynchronize(s));
-                fprintf(stderr, "[trsv stats] H=%d kind=%d per item: near %.3f ms, wait %.3f ms, sweep+stage %.3f ms\n", H,
-                        kind, h[0] / 1e5 / B, h[1] / 1e5 / B, h[2] / 1e5 / B);
+                fprintf(stderr, "[trsv stats] H=%d kind=%d per item (critical workgroup): near %.3f ms, publish %.3f ms, "
+                        "wait for helpers %.3f ms, barrier %.3f ms, sweep %.3f ms, end barrier %.3f ms\n", H, kind,
+                        h[0] / 1e5 / B, h[4] / 1e5 / B, h[1] / 1e5 / B, h[5] / 1e5 / B, h[2] / 1e5 / B, h[3] / 1e5 / B);
             }
             return OM_OK;
         }
