@@ -47,7 +47,7 @@ constexpr int IWAVES = IT / 64;
 constexpr int WBITS_MAX = 1 << 16;  // largest band window (lb + ub + 1)
 constexpr int RADIX_BITS = 11;
 constexpr int FLAG_STRIDE = 32;
-constexpr int UF = 4;               // U-row entries per thread in flight in an update     // one 128-byte line per row's ready flag
+constexpr int UF = 8;               // U-row entries per thread in flight in an update
 constexpr int RADIX = 1 << RADIX_BITS;
 
 struct IlutDevArgs {
@@ -75,6 +75,8 @@ struct IlutDevArgs {
     double2* work;          // gridDim * W
     int32_t* next_row;
     int32_t* abort_flag;
+    unsigned long long* tstat;  // diagnostics (nullable): wall-clock ticks and counts per phase
+    int32_t acq_fence;      // agent-scope acquire fence after observing finished rows
     int32_t* status;        // [0] first breakdown row + 1 (0 = none), [1] repaired pivots,
                             // [2], [3] row + 1 of the waiter and of the awaited row on a timeout,
                             // [4] row + 1 that found inconsistent row data
@@ -229,6 +231,228 @@ __device__ unsigned long long select_kth(const double2* w, const uint32_t* bits,
     return prefix;
 }
 
+// Sum over the block of one int per thread (wave-uniform result).
+__device__ inline int block_sum(int v, int* sbuf) {
+    int tot;
+    (void)block_scan(v, &tot, sbuf);
+    return tot;
+}
+
+// Radix select over keys held in LDS (0 = not a candidate): the key K of the
+// lfil-th largest and, in *n_gt, how many keys exceed K.  Same digits and
+// tie rule as select_kth.  Requires 1 <= lfil < number of candidates.
+__device__ unsigned long long select_kth_lds(const unsigned long long* key, int cnt, int lfil, int* n_gt,
+                                             unsigned int* hist, int* sbuf) {
+    unsigned long long prefix = 0, pmask = 0;
+    int need = lfil, above = 0;
+    for (int shift = 64 - RADIX_BITS; shift > -RADIX_BITS; shift -= RADIX_BITS) {
+        const int sh = shift < 0 ? 0 : shift;
+        const int nb = shift < 0 ? RADIX_BITS + shift : RADIX_BITS;
+        const unsigned int dmask = (1u << nb) - 1u;
+        for (int t = threadIdx.x; t < RADIX; t += IT) hist[t] = 0;
+        __syncthreads();
+        for (int t = threadIdx.x; t < cnt; t += IT) {
+            const unsigned long long k = key[t];
+            if (k == 0ull || (k & pmask) != prefix) continue;
+            atomicAdd(&hist[(unsigned int)(k >> sh) & dmask], 1u);
+        }
+        __syncthreads();
+        int own = 0;
+        int c8[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int d = (int)dmask - 8 * threadIdx.x - j;
+            c8[j] = d >= 0 ? (int)hist[d] : 0;
+            own += c8[j];
+        }
+        int tot;
+        const int before = block_scan(own, &tot, sbuf + 2);
+        if (before < need && need <= before + own) {
+            int acc = before;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                if (acc + c8[j] >= need) {
+                    sbuf[0] = (int)dmask - 8 * threadIdx.x - j;
+                    sbuf[1] = acc;
+                    break;
+                }
+                acc += c8[j];
+            }
+        }
+        __syncthreads();
+        const int d = __builtin_amdgcn_readfirstlane(sbuf[0]);
+        const int acc = __builtin_amdgcn_readfirstlane(sbuf[1]);
+        const int in_d = __builtin_amdgcn_readfirstlane((int)hist[d]);
+        __syncthreads();
+        above += acc;
+        need -= acc;
+        prefix |= ((unsigned long long)d) << sh;
+        pmask |= ((unsigned long long)dmask) << sh;
+        if (need == in_d && prefix != 0ull) {
+            // every key of the chosen digit range is kept: the lfil largest are
+            // exactly the keys >= prefix, so K = prefix - 1 with lfil keys above
+            // it selects them and leaves no tie to take
+            *n_gt = lfil;
+            return prefix - 1ull;
+        }
+    }
+    *n_gt = above;
+    return prefix;
+}
+
+constexpr int CAND_MAX = 6144;   // entries of one triangle staged in LDS for the cap
+
+struct SideShared {
+    unsigned long long key[CAND_MAX];
+    uint16_t pos[CAND_MAX];
+};
+
+// Dropping and cap of one triangle of row i, window positions [p0, p1), and
+// output of the kept entries in column order to (ocol, oval); returns how
+// many were kept, and sets *bad when check_finite and a kept entry is not
+// finite.  The present positions and the keys (squared moduli; 0 = dropped)
+// are staged in LDS once, so the window is read twice (keys, output) however
+// many digit passes the cap takes; a triangle with more than CAND_MAX present
+// entries reads its keys from the window in every pass instead.
+__device__ int output_side(const double2* w, const uint32_t* bits, int p0, int p1, int64_t lo, double tau2, int lfil,
+                           int32_t* ocol, double2* oval, bool check_finite, bool* bad, SideShared& ss,
+                           unsigned int* hist, int* sbuf) {
+    const int tid = threadIdx.x;
+    // present positions per thread over a contiguous range of bitmap words
+    const int wlo = p0 >> 5, whi = p1 > p0 ? ((p1 - 1) >> 5) + 1 : wlo;
+    const int nw = whi - wlo, wch = (nw + IT - 1) / IT;
+    const int q0 = wlo + tid * wch, q1 = min(whi, q0 + wch);
+    auto word_at = [&](int q) -> uint32_t {
+        uint32_t x = bits[q];
+        const int b = q * 32;
+        if (p0 > b) x &= p0 - b >= 32 ? 0u : (~0u << (p0 - b));
+        if (p1 < b + 32) x &= p1 - b <= 0 ? 0u : (~0u >> (32 - (p1 - b)));
+        return x;
+    };
+    int mine = 0;
+    for (int q = q0; q < q1; ++q) mine += __popc(word_at(q));
+    int present;
+    const int off = block_scan(mine, &present, sbuf);
+    if (present <= CAND_MAX) {
+        {
+            int j = off;
+            for (int q = q0; q < q1; ++q) {
+                uint32_t x = word_at(q);
+                while (x) {
+                    const int b = __ffs((int)x) - 1;
+                    x &= x - 1u;
+                    ss.pos[j++] = (uint16_t)(q * 32 + b);
+                }
+            }
+        }
+        __syncthreads();
+        int live = 0;
+        for (int t0 = tid; t0 < present; t0 += 4 * IT) {
+            double2 v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int t = t0 + u * IT;
+                if (t < present) v[u] = w[ss.pos[t]];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int t = t0 + u * IT;
+                if (t < present) {
+                    const double m2 = v[u].x * v[u].x + v[u].y * v[u].y;
+                    const bool cand = !(m2 == 0.0 || m2 < tau2);
+                    ss.key[t] = cand ? key_of(m2) : 0ull;
+                    live += cand;
+                }
+            }
+        }
+        const int tot = block_sum(live, sbuf);   // (its barriers also order the key writes)
+        const bool cap = tot > lfil;
+        unsigned long long K = 0ull;
+        int n_gt = 0;
+        // lfil = 0 keeps nothing: K above every key, no ties taken
+        if (cap) K = lfil > 0 ? select_kth_lds(ss.key, present, lfil, &n_gt, hist, sbuf + 4) : ~0ull;
+        const int ch = (present + IT - 1) / IT;
+        const int c0 = tid * ch, c1 = min(present, c0 + ch);
+        int keep = 0, eq = 0;
+        for (int t = c0; t < c1; ++t) {
+            const unsigned long long k = ss.key[t];
+            if (k == 0ull) continue;
+            if (!cap || k > K) ++keep; else if (k == K) ++eq;
+        }
+        int tmp;
+        const int eq_before = block_scan(eq, &tmp, sbuf);
+        // ties at K: the first (lfil - n_gt) in column order are kept
+        const int take = cap ? max(0, min(eq, lfil - n_gt - eq_before)) : 0;
+        int total = 0;
+        const int out = block_scan(keep + take, &total, sbuf);
+        int written = 0, e = 0;
+        for (int t = c0; t < c1; ++t) {
+            const unsigned long long k = ss.key[t];
+            if (k == 0ull) continue;
+            bool kp = !cap || k > K;
+            if (cap && k == K) kp = e++ < take;
+            if (kp) {
+                const int pp = ss.pos[t];
+                const double2 v = w[pp];
+                if (check_finite && (!isfinite(v.x) || !isfinite(v.y))) *bad = true;
+                ocol[out + written] = (int32_t)(lo + pp);
+                oval[out + written] = v;
+                ++written;
+            }
+        }
+        __syncthreads();   // the staging arrays are reused by the next call
+        return total;
+    }
+    // more present entries than the staging arrays hold: keys from the window
+    int cnt = 0;
+    for (int pp = p0 + tid; pp < p1; pp += IT) {
+        if (!((bits[pp >> 5] >> (pp & 31)) & 1u)) continue;
+        const double2 v = w[pp];
+        const double m2 = v.x * v.x + v.y * v.y;
+        if (m2 == 0.0 || m2 < tau2) continue;
+        ++cnt;
+    }
+    const int tot = block_sum(cnt, sbuf);
+    const bool cap = tot > lfil;
+    unsigned long long K = 0ull;
+    int n_gt = 0;
+    if (cap) K = lfil > 0 ? select_kth(w, bits, p0, p1, tau2, lfil, &n_gt, hist, sbuf + 4) : ~0ull;
+    const int chunk = (p1 - p0 + IT - 1) / IT;
+    const int c0 = p0 + tid * chunk, c1 = min(p1, c0 + chunk);
+    int keep = 0, eq = 0;
+    for (int pp = c0; pp < c1; ++pp) {
+        if (!((bits[pp >> 5] >> (pp & 31)) & 1u)) continue;
+        const double2 v = w[pp];
+        const double m2 = v.x * v.x + v.y * v.y;
+        if (m2 == 0.0 || m2 < tau2) continue;
+        const unsigned long long key = key_of(m2);
+        if (!cap || key > K) ++keep; else if (key == K) ++eq;
+    }
+    int tmp;
+    const int eq_before = block_scan(eq, &tmp, sbuf);
+    const int take = cap ? max(0, min(eq, lfil - n_gt - eq_before)) : 0;
+    int total = 0;
+    const int out = block_scan(keep + take, &total, sbuf);
+    int written = 0, e = 0;
+    for (int pp = c0; pp < c1; ++pp) {
+        if (!((bits[pp >> 5] >> (pp & 31)) & 1u)) continue;
+        const double2 v = w[pp];
+        const double m2 = v.x * v.x + v.y * v.y;
+        if (m2 == 0.0 || m2 < tau2) continue;
+        const unsigned long long key = key_of(m2);
+        bool kp = !cap || key > K;
+        if (cap && key == K) kp = e++ < take;
+        if (kp) {
+            if (check_finite && (!isfinite(v.x) || !isfinite(v.y))) *bad = true;
+            ocol[out + written] = (int32_t)(lo + pp);
+            oval[out + written] = v;
+            ++written;
+        }
+    }
+    __syncthreads();
+    return total;
+}
+
 __global__ __launch_bounds__(IT) void ilut_row_kernel(IlutDevArgs a) {
     __shared__ uint32_t bits[WBITS_MAX / 32];
     __shared__ unsigned int hist[RADIX];
@@ -238,6 +462,7 @@ __global__ __launch_bounds__(IT) void ilut_row_kernel(IlutDevArgs a) {
     __shared__ int s_k[2], s_flag[2], s_ulen[2];
     __shared__ int64_t s_uoff[2];
     __shared__ double2 s_m[2];
+    __shared__ SideShared side;
     // Every loop below is controlled by wave-uniform values (read with
     // readfirstlane from shared memory) and has no early exit; per-lane work
     // (lane 0 fetching the next row, publishing a row) sits between two
@@ -249,6 +474,11 @@ __global__ __launch_bounds__(IT) void ilut_row_kernel(IlutDevArgs a) {
     const int W = a.W, nwords = (W + 31) >> 5;
     double2* w = a.work + (int64_t)blockIdx.x * a.wstride;
 
+    // diagnostics (thread 0): ticks in the pivot steps of wave 0, in waits
+    // for unfinished rows, in updates and in the dropping and output; counts
+    // of rows, steps, updating steps and updated entries
+    unsigned long long st_piv = 0, st_wait = 0, st_upd = 0, st_fin = 0, st_rows = 0, st_steps = 0, st_usteps = 0,
+                       st_ent = 0, tq = 0;
     if (tid == 0) {
         s_row = atomicAdd(a.next_row, 1);
         s_stop = ld_flag(a.abort_flag);
@@ -295,6 +525,7 @@ __global__ __launch_bounds__(IT) void ilut_row_kernel(IlutDevArgs a) {
         int par = 0;
         int going = 1;
         while (going) {
+            if (a.tstat && tid == 0) tq = wall_clock64();
             if (wave == 0) {
                 int found = -1;
                 for (int base = (kprev + 1) >> 5; base <= ((dpos - 1) >> 5) && found < 0; base += 64) {
@@ -331,17 +562,20 @@ __global__ __launch_bounds__(IT) void ilut_row_kernel(IlutDevArgs a) {
                             rdy = rmask & 1ull;
                             // rows seen finished: their data, read below with ordinary
                             // loads, must not come from lines cached before
-                            if (rmask) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                            if (rmask && a.acq_fence) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                         }
                         if (!rdy) {
                             int ok = 1;
-                            if (lane == 0)
+                            if (lane == 0) {
+                                const unsigned long long tw = a.tstat ? wall_clock64() : 0;
                                 ok = wait_flag(a.ready + k * FLAG_STRIDE, (int32_t)a.epoch, a.abort_flag, a.wait_ticks,
                                                a.status + 2, i, k);
+                                if (a.tstat) st_wait += wall_clock64() - tw;
+                            }
                             ok = __shfl(ok, 0, 64);
                             if (ok) {
                                 rmask |= 1ull;
-                                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                                if (a.acq_fence) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                             } else {
                                 flag = -1;
                             }
@@ -375,6 +609,7 @@ __global__ __launch_bounds__(IT) void ilut_row_kernel(IlutDevArgs a) {
                 }
             }
             __syncthreads();
+            if (a.tstat && tid == 0) { const unsigned long long t = wall_clock64(); st_piv += t - tq; tq = t; ++st_steps; }
             const int kp = __builtin_amdgcn_readfirstlane(s_k[par]);
             const int fl = __builtin_amdgcn_readfirstlane(s_flag[par]);
             if (kp < 0 || fl < 0) {
@@ -442,6 +677,7 @@ __global__ __launch_bounds__(IT) void ilut_row_kernel(IlutDevArgs a) {
                     stop = 1;
                     if (tid == 0) __hip_atomic_store(a.status + 4, (int32_t)(i + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 }
+                if (a.tstat && tid == 0) { st_upd += wall_clock64() - tq; ++st_usteps; st_ent += len; }
             }
             if (stop && fl == -2 && tid == 0)
                 __hip_atomic_store(a.status + 4, (int32_t)(i + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -450,85 +686,20 @@ __global__ __launch_bounds__(IT) void ilut_row_kernel(IlutDevArgs a) {
             going = __builtin_amdgcn_readfirstlane(going);
             stop = __builtin_amdgcn_readfirstlane(stop);
         }
+        if (a.tstat && tid == 0) tq = wall_clock64();
         if (stop) {
             if (tid == 0) publish_flag(a.abort_flag, 1);
         } else {
-            // 3. dropping, cap, output
-            int n_gt_l = 0, n_gt_u = 0;
-            unsigned long long Kl = 0ull, Ku = 0ull;
-            int cl = 0, cu = 0;   // candidate counts per thread
-            for (int p = tid; p < W; p += IT) {
-                if (p == dpos || !((bits[p >> 5] >> (p & 31)) & 1u)) continue;
-                const double2 v = w[p];
-                const double m2 = v.x * v.x + v.y * v.y;
-                if (m2 == 0.0 || m2 < tau2) continue;
-                if (p < dpos) ++cl; else ++cu;
-            }
-            int totl = 0, totu = 0;
-            (void)block_scan(cl, &totl, sbuf);
-            (void)block_scan(cu, &totu, sbuf);
-            const bool cap_l = totl > lfil, cap_u = totu > lfil;
-            // lfil = 0 keeps nothing: K above every key, no ties taken
-            if (cap_l) Kl = lfil > 0 ? select_kth(w, bits, 0, dpos, tau2, lfil, &n_gt_l, hist, sbuf + 4) : ~0ull;
-            if (cap_u) Ku = lfil > 0 ? select_kth(w, bits, dpos + 1, W, tau2, lfil, &n_gt_u, hist, sbuf + 4) : ~0ull;
-            // compaction in column order: each thread takes a contiguous chunk
-            const int chunk = (W + IT - 1) / IT;
-            const int c0 = tid * chunk, c1 = min(W, c0 + chunk);
-            int keep_l = 0, keep_u = 0, eq_l = 0, eq_u = 0;
-            for (int p = c0; p < c1; ++p) {
-                if (p == dpos || !((bits[p >> 5] >> (p & 31)) & 1u)) continue;
-                const double2 v = w[p];
-                const double m2 = v.x * v.x + v.y * v.y;
-                if (m2 == 0.0 || m2 < tau2) continue;
-                const unsigned long long key = key_of(m2);
-                if (p < dpos) {
-                    if (!cap_l || key > Kl) ++keep_l; else if (key == Kl) ++eq_l;
-                } else {
-                    if (!cap_u || key > Ku) ++keep_u; else if (key == Ku) ++eq_u;
-                }
-            }
-            int tmp;
-            const int eq_l_before = block_scan(eq_l, &tmp, sbuf);
-            const int eq_u_before = block_scan(eq_u, &tmp, sbuf);
-            // ties at K: the first (lfil - n_gt) in column order are kept
-            const int take_l = cap_l ? max(0, min(eq_l, lfil - n_gt_l - eq_l_before)) : 0;
-            const int take_u = cap_u ? max(0, min(eq_u, lfil - n_gt_u - eq_u_before)) : 0;
-            int tot_l = 0, tot_u = 0;
-            const int out_l = block_scan(keep_l + take_l, &tot_l, sbuf);
-            const int out_u = block_scan(keep_u + take_u, &tot_u, sbuf);
-            // diagonal, breakdown check
-            double2 dg = make_double2(0.0, 0.0);
-            if ((bits[dpos >> 5] >> (dpos & 31)) & 1u) dg = w[dpos];
+            // 3. dropping, cap, output.  The U row and the pivot come first and
+            // are published at once (later rows wait only for them); the L row
+            // is written afterwards.
             const int64_t lb0 = a.l_off[i], ub0 = a.u_off[i];
-            int written_l = 0, written_u = 0, el = 0, eu = 0;
             bool bad = false;
-            for (int p = c0; p < c1; ++p) {
-                if (p == dpos || !((bits[p >> 5] >> (p & 31)) & 1u)) continue;
-                const double2 v = w[p];
-                const double m2 = v.x * v.x + v.y * v.y;
-                if (m2 == 0.0 || m2 < tau2) continue;
-                const unsigned long long key = key_of(m2);
-                const int32_t c = (int32_t)(lo + p);
-                if (p < dpos) {
-                    bool keep = !cap_l || key > Kl;
-                    if (cap_l && key == Kl) keep = el++ < take_l;
-                    if (keep) {
-                        a.l_col[lb0 + out_l + written_l] = c;
-                        a.l_val[lb0 + out_l + written_l] = v;
-                        ++written_l;
-                    }
-                } else {
-                    bool keep = !cap_u || key > Ku;
-                    if (cap_u && key == Ku) keep = eu++ < take_u;
-                    if (keep) {
-                        if (!isfinite(v.x) || !isfinite(v.y)) bad = true;
-                        a.u_col[ub0 + 1 + out_u + written_u] = c;
-                        a.u_val[ub0 + 1 + out_u + written_u] = v;
-                        ++written_u;
-                    }
-                }
-            }
+            const int nu = output_side(w, bits, dpos + 1, W, lo, tau2, lfil, a.u_col + ub0 + 1, a.u_val + ub0 + 1, true,
+                                       &bad, side, hist, sbuf);
             if (tid == 0) {
+                double2 dg = make_double2(0.0, 0.0);
+                if ((bits[dpos >> 5] >> (dpos & 31)) & 1u) dg = w[dpos];
                 if (!isfinite(dg.x) || !isfinite(dg.y)) bad = true;
                 const double fl = 1e-14 * rowinf;
                 const double dmag = sqrt(dg.x * dg.x + dg.y * dg.y);
@@ -541,8 +712,7 @@ __global__ __launch_bounds__(IT) void ilut_row_kernel(IlutDevArgs a) {
                 a.u_col[ub0] = (int32_t)i;
                 a.u_val[ub0] = dg;
                 a.udiag[i] = dg;
-                a.l_len[i] = tot_l;
-                a.u_len[i] = tot_u + 1;
+                a.u_len[i] = nu + 1;
             }
             if (block_or(bad, s_or)) {
                 stop = 1;
@@ -550,14 +720,20 @@ __global__ __launch_bounds__(IT) void ilut_row_kernel(IlutDevArgs a) {
                     atomicCAS(a.status, 0, (int32_t)(i + 1));
                     publish_flag(a.abort_flag, 1);
                 }
-            } else if (tid == 0) {
-                // the release writes the row back from L2 before the flag
-                publish_flag(a.ready + i * FLAG_STRIDE, (int32_t)a.epoch);
-                if ((i & 4095) == 0) __hip_atomic_store(a.host_progress, (int32_t)i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            } else {
+                if (tid == 0) {
+                    // the release writes the row back from L2 before the flag
+                    publish_flag(a.ready + i * FLAG_STRIDE, (int32_t)a.epoch);
+                    if ((i & 4095) == 0) __hip_atomic_store(a.host_progress, (int32_t)i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                }
+                const int nl = output_side(w, bits, 0, dpos, lo, tau2, lfil, a.l_col + lb0, a.l_val + lb0, false, &bad,
+                                           side, hist, sbuf);
+                if (tid == 0) a.l_len[i] = nl;
             }
         }
         // next row
         __syncthreads();
+        if (a.tstat && tid == 0) { st_fin += wall_clock64() - tq; ++st_rows; }
         if (tid == 0) {
             s_row = atomicAdd(a.next_row, 1);
             s_stop = ld_flag(a.abort_flag);
@@ -565,6 +741,16 @@ __global__ __launch_bounds__(IT) void ilut_row_kernel(IlutDevArgs a) {
         __syncthreads();
         i = __builtin_amdgcn_readfirstlane(s_row);
         stop = __builtin_amdgcn_readfirstlane(stop | s_stop);
+    }
+    if (a.tstat && tid == 0) {
+        atomicAdd(a.tstat + 0, st_piv);
+        atomicAdd(a.tstat + 1, st_wait);
+        atomicAdd(a.tstat + 2, st_upd);
+        atomicAdd(a.tstat + 3, st_fin);
+        atomicAdd(a.tstat + 4, st_rows);
+        atomicAdd(a.tstat + 5, st_steps);
+        atomicAdd(a.tstat + 6, st_usteps);
+        atomicAdd(a.tstat + 7, st_ent);
     }
 }
 
@@ -645,6 +831,16 @@ om_status ilut_factor_dev(const om_csr* A, int item, double drop_tol, double fil
     if (const char* e = getenv("OMSS_ILUT_WAIT_S")) wait_s = std::max(0.1, atof(e));
     a.wait_ticks = (long long)((double)std::max(clk_khz, 1000) * 1000.0 * wait_s);
     a.next_row = misc.p; a.abort_flag = misc.p + 32; a.status = misc.p + 2;
+    a.acq_fence = 1;
+    if (const char* e = getenv("OMSS_ILUT_FENCE")) a.acq_fence = atoi(e) != 0;
+    DevBuf<unsigned long long> tstat;
+    a.tstat = nullptr;
+    if (getenv("OMSS_ILUT_STATS")) {
+        OM_TRY(tstat.alloc(8));
+        OM_HIP(hipMemsetAsync(tstat.p, 0, tstat.bytes(), s));
+        OM_HIP(hipStreamSynchronize(s));
+        a.tstat = tstat.p;
+    }
     // progress word in pinned host memory, written by the kernel now and then
     int32_t* hprog = nullptr;
     OM_HIP(hipHostMalloc((void**)&hprog, 256, hipHostMallocMapped | hipHostMallocCoherent));
@@ -682,6 +878,16 @@ om_status ilut_factor_dev(const om_csr* A, int item, double drop_tol, double fil
     if (verbose)
         fprintf(stderr, "[omss] device ILUT: n %lld, window %lld, %d workgroups, %.3f s\n", (long long)n, (long long)W, G,
                 std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
+    if (a.tstat) {
+        unsigned long long h[8];
+        OM_HIP(hipMemcpy(h, a.tstat, sizeof h, hipMemcpyDeviceToHost));
+        const double us = 1e6 / ((double)std::max(clk_khz, 1000) * 1000.0);
+        const double rows = (double)std::max(1ull, h[4]);
+        fprintf(stderr, "[ilut stats] %d workgroups, window %lld: per row %.1f steps (%.1f updating, %.0f entries); "
+                "per row us: pivot steps %.1f (of which waiting %.1f), updates %.1f, dropping and output %.1f\n", G,
+                (long long)W, h[5] / rows, h[6] / rows, h[7] / rows, h[0] * us / rows, h[1] * us / rows,
+                h[2] * us / rows, h[3] * us / rows);
+    }
     if (hs[2] != 0) {
         if (err) *err = "ILUT breakdown: non-finite pivot or entry in row " + std::to_string(hs[2] - 1) +
                         " (the incomplete factorisation is unstable for this drop tolerance and fill)";
