@@ -14,6 +14,7 @@ struct HostFactor;
 // entries right of it, columns increasing).
 struct DevFactor {
     int64_t n = 0, nnz_l = 0, nnz_u = 0, repaired = 0;
+    int64_t upd_entries = 0;   // U-row entries read by the eliminations
     DevBuf<int64_t> l_off, u_off;
     DevBuf<int32_t> l_len, u_len, l_col, u_col;
     DevBuf<double2> l_val, u_val;

@@ -37,6 +37,7 @@
 #include "ilu.hpp"
 #include "ilut.hpp"
 #include "kernels.hpp"
+#include "profile.hpp"
 
 #pragma clang fp contract(off)
 
@@ -47,7 +48,7 @@ constexpr int IWAVES = IT / 64;
 constexpr int WBITS_MAX = 1 << 16;  // largest band window (lb + ub + 1)
 constexpr int RADIX_BITS = 11;
 constexpr int FLAG_STRIDE = 32;
-constexpr int UF = 8;               // U-row entries per thread in flight in an update
+constexpr int UF = 4;               // U-row entries per thread in flight in an update
 constexpr int RADIX = 1 << RADIX_BITS;
 
 struct IlutDevArgs {
@@ -77,7 +78,8 @@ struct IlutDevArgs {
     int32_t* abort_flag;
     unsigned long long* tstat;  // diagnostics (nullable): wall-clock ticks and counts per phase
     int32_t acq_fence;      // agent-scope acquire fence after observing finished rows
-    int32_t* status;        // [0] first breakdown row + 1 (0 = none), [1] repaired pivots,
+    int32_t max_pause;      // longest back-off of a wait, in units of s_sleep(1)
+    int32_t* status;        // [0] first breakdown row + 1 (0 = none), [1] repaired pivots, [38..39] U-row entries read,
                             // [2], [3] row + 1 of the waiter and of the awaited row on a timeout,
                             // [4] row + 1 that found inconsistent row data
 };
@@ -116,7 +118,7 @@ __device__ inline void publish_flag(int32_t* p, int32_t v) {
 // abort flag, read by every waiter, is polled only every 16th round, with a
 // growing pause between polls, to keep the flag lines from becoming hot spots.
 __device__ bool wait_flag(int32_t* f, int32_t v, int32_t* abort_flag, long long ticks, int32_t* diag,
-                          int64_t waiter, int64_t awaited) {
+                          int64_t waiter, int64_t awaited, unsigned int max_pause) {
     const long long t0 = wall_clock64();
     unsigned int pause = 1;
     for (unsigned int it = 0; ld_flag(f) != v; ++it) {
@@ -129,9 +131,9 @@ __device__ bool wait_flag(int32_t* f, int32_t v, int32_t* abort_flag, long long 
                 return false;
             }
         }
-        // exponential back-off, 64 to 8192 cycles
+        // exponential back-off from 64 cycles up to 64 * max_pause
         for (unsigned int q = 0; q < pause; ++q) __builtin_amdgcn_s_sleep(1);
-        if (pause < 128) pause <<= 1;
+        if (pause < max_pause) pause <<= 1;
     }
     return true;
 }
@@ -302,10 +304,46 @@ __device__ unsigned long long select_kth_lds(const unsigned long long* key, int 
 
 constexpr int CAND_MAX = 6144;   // entries of one triangle staged in LDS for the cap
 
+constexpr int RPT = 8;           // candidates per thread held in registers (strided by the block size)
+
 struct SideShared {
     unsigned long long key[CAND_MAX];
     uint16_t pos[CAND_MAX];
+    int cnt[RPT][IWAVES];        // per round and wave: flags set (scans in candidate order)
+    unsigned long long tph[12];  // diagnostics (thread 0): [0..3] ticks in positions, keys, select, output;
+                                 // [4] staged calls, [6] calls reading the window, [11] capped staged calls
+    int on;                      // diagnostics enabled
 };
+
+// Rank of each thread's flagged candidates in candidate order, candidate
+// u * IT + tid being flag f[u]: returns in r[u] the number of flagged
+// candidates before it and the total in *total.  Wave ballots, one barrier.
+__device__ inline void strided_rank(const bool (&f)[RPT], int (&r)[RPT], int* total, SideShared& ss) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    unsigned long long m[RPT];
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) {
+        m[u] = __ballot(f[u]);
+        if (lane == 0) ss.cnt[u][wave] = __popcll(m[u]);
+    }
+    __syncthreads();
+    int base = 0;
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) {
+        int before_w = 0, row = 0;
+#pragma unroll
+        for (int q = 0; q < IWAVES; ++q) {
+            const int c = ss.cnt[u][q];
+            before_w += q < wave ? c : 0;
+            row += c;
+        }
+        const unsigned long long below = lane ? (m[u] & (~0ull >> (64 - lane))) : 0ull;
+        r[u] = base + before_w + __popcll(below);
+        base += row;
+    }
+    *total = __builtin_amdgcn_readfirstlane(base);
+    __syncthreads();   // cnt is reused by the next call
+}
 
 // Dropping and cap of one triangle of row i, window positions [p0, p1), and
 // output of the kept entries in column order to (ocol, oval); returns how
@@ -329,6 +367,10 @@ __device__ int output_side(const double2* w, const uint32_t* bits, int p0, int p
         if (p1 < b + 32) x &= p1 - b <= 0 ? 0u : (~0u >> (32 - (p1 - b)));
         return x;
     };
+    unsigned long long tt = (ss.on && tid == 0) ? wall_clock64() : 0;
+    auto phase = [&](int k) {
+        if (ss.on && tid == 0) { const unsigned long long t = wall_clock64(); ss.tph[k] += t - tt; tt = t; }
+    };
     int mine = 0;
     for (int q = q0; q < q1; ++q) mine += __popc(word_at(q));
     int present;
@@ -346,17 +388,22 @@ __device__ int output_side(const double2* w, const uint32_t* bits, int p0, int p
             }
         }
         __syncthreads();
+        phase(0);
+        // candidate t is handled by thread t % IT in round t / IT, so that the
+        // lanes of a wave touch consecutive LDS words and window entries;
+        // rounds go in groups of RPT
+        const int rounds = (present + IT - 1) / IT, groups = (rounds + RPT - 1) / RPT;
         int live = 0;
-        for (int t0 = tid; t0 < present; t0 += 4 * IT) {
-            double2 v[4];
+        for (int gq = 0; gq < groups; ++gq) {
+            double2 v[RPT];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int t = t0 + u * IT;
+            for (int u = 0; u < RPT; ++u) {
+                const int t = (gq * RPT + u) * IT + tid;
                 if (t < present) v[u] = w[ss.pos[t]];
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int t = t0 + u * IT;
+            for (int u = 0; u < RPT; ++u) {
+                const int t = (gq * RPT + u) * IT + tid;
                 if (t < present) {
                     const double m2 = v[u].x * v[u].x + v[u].y * v[u].y;
                     const bool cand = !(m2 == 0.0 || m2 < tau2);
@@ -366,44 +413,71 @@ __device__ int output_side(const double2* w, const uint32_t* bits, int p0, int p
             }
         }
         const int tot = block_sum(live, sbuf);   // (its barriers also order the key writes)
+        phase(1);
         const bool cap = tot > lfil;
-        unsigned long long K = 0ull;
-        int n_gt = 0;
-        // lfil = 0 keeps nothing: K above every key, no ties taken
-        if (cap) K = lfil > 0 ? select_kth_lds(ss.key, present, lfil, &n_gt, hist, sbuf + 4) : ~0ull;
-        const int ch = (present + IT - 1) / IT;
-        const int c0 = tid * ch, c1 = min(present, c0 + ch);
-        int keep = 0, eq = 0;
-        for (int t = c0; t < c1; ++t) {
-            const unsigned long long k = ss.key[t];
-            if (k == 0ull) continue;
-            if (!cap || k > K) ++keep; else if (k == K) ++eq;
-        }
-        int tmp;
-        const int eq_before = block_scan(eq, &tmp, sbuf);
-        // ties at K: the first (lfil - n_gt) in column order are kept
-        const int take = cap ? max(0, min(eq, lfil - n_gt - eq_before)) : 0;
-        int total = 0;
-        const int out = block_scan(keep + take, &total, sbuf);
-        int written = 0, e = 0;
-        for (int t = c0; t < c1; ++t) {
-            const unsigned long long k = ss.key[t];
-            if (k == 0ull) continue;
-            bool kp = !cap || k > K;
-            if (cap && k == K) kp = e++ < take;
-            if (kp) {
-                const int pp = ss.pos[t];
-                const double2 v = w[pp];
-                if (check_finite && (!isfinite(v.x) || !isfinite(v.y))) *bad = true;
-                ocol[out + written] = (int32_t)(lo + pp);
-                oval[out + written] = v;
-                ++written;
+        if (ss.on && tid == 0) ss.tph[11] += cap;
+        if (cap) {
+            int n_gt = 0;
+            // lfil = 0 keeps nothing: K above every key, no ties taken
+            const unsigned long long K = lfil > 0 ? select_kth_lds(ss.key, present, lfil, &n_gt, hist, sbuf + 4) : ~0ull;
+            phase(2);
+            // ties at K: the first (lfil - n_gt) in column order are kept; the
+            // keys are replaced by the decision (1 kept, 0 not)
+            const int take = lfil - n_gt;
+            int base = 0;
+            for (int gq = 0; gq < groups; ++gq) {
+                bool f[RPT];
+                unsigned long long kk[RPT];
+#pragma unroll
+                for (int u = 0; u < RPT; ++u) {
+                    const int t = (gq * RPT + u) * IT + tid;
+                    kk[u] = t < present ? ss.key[t] : 0ull;
+                    f[u] = kk[u] != 0ull && kk[u] == K;
+                }
+                int r[RPT], tg;
+                strided_rank(f, r, &tg, ss);
+#pragma unroll
+                for (int u = 0; u < RPT; ++u) {
+                    const int t = (gq * RPT + u) * IT + tid;
+                    if (t < present) ss.key[t] = (kk[u] != 0ull && (kk[u] > K || (f[u] && base + r[u] < take))) ? 1ull : 0ull;
+                }
+                base += tg;
             }
+            __syncthreads();
         }
-        __syncthreads();   // the staging arrays are reused by the next call
-        return total;
+        // output: ranks of the kept candidates in column order, then the
+        // loads and stores of a group (consecutive lanes, consecutive ranks)
+        int base = 0;
+        for (int gq = 0; gq < groups; ++gq) {
+            bool f[RPT];
+            int pp[RPT];
+#pragma unroll
+            for (int u = 0; u < RPT; ++u) {
+                const int t = (gq * RPT + u) * IT + tid;
+                f[u] = t < present && ss.key[t] != 0ull;
+                pp[u] = t < present ? (int)ss.pos[t] : 0;
+            }
+            int r[RPT], tg;
+            strided_rank(f, r, &tg, ss);
+            double2 v[RPT];
+#pragma unroll
+            for (int u = 0; u < RPT; ++u)
+                if (f[u]) v[u] = w[pp[u]];
+#pragma unroll
+            for (int u = 0; u < RPT; ++u)
+                if (f[u]) {
+                    if (check_finite && (!isfinite(v[u].x) || !isfinite(v[u].y))) *bad = true;
+                    ocol[base + r[u]] = (int32_t)(lo + pp[u]);
+                    oval[base + r[u]] = v[u];
+                }
+            base += tg;
+        }
+        phase(3);
+        if (ss.on && tid == 0) ++ss.tph[4];
+        return base;
     }
     // more present entries than the staging arrays hold: keys from the window
+    if (ss.on && tid == 0) ++ss.tph[6];
     int cnt = 0;
     for (int pp = p0 + tid; pp < p1; pp += IT) {
         if (!((bits[pp >> 5] >> (pp & 31)) & 1u)) continue;
@@ -453,7 +527,7 @@ __device__ int output_side(const double2* w, const uint32_t* bits, int p0, int p
     return total;
 }
 
-__global__ __launch_bounds__(IT) void ilut_row_kernel(IlutDevArgs a) {
+__global__ __launch_bounds__(IT, 2) void ilut_row_kernel(IlutDevArgs a) {
     __shared__ uint32_t bits[WBITS_MAX / 32];
     __shared__ unsigned int hist[RADIX];
     __shared__ int sbuf[16];
@@ -478,7 +552,12 @@ __global__ __launch_bounds__(IT) void ilut_row_kernel(IlutDevArgs a) {
     // for unfinished rows, in updates and in the dropping and output; counts
     // of rows, steps, updating steps and updated entries
     unsigned long long st_piv = 0, st_wait = 0, st_upd = 0, st_fin = 0, st_rows = 0, st_steps = 0, st_usteps = 0,
-                       st_ent = 0, tq = 0;
+                       st_ent = 0, st_finu = 0, tq = 0;
+    unsigned long long n_upd = 0;   // U-row entries read by this workgroup's eliminations (thread 0)
+    if (tid == 0) {
+        side.on = a.tstat != nullptr;
+        for (int k = 0; k < 12; ++k) side.tph[k] = 0;
+    }
     if (tid == 0) {
         s_row = atomicAdd(a.next_row, 1);
         s_stop = ld_flag(a.abort_flag);
@@ -569,7 +648,7 @@ __global__ __launch_bounds__(IT) void ilut_row_kernel(IlutDevArgs a) {
                             if (lane == 0) {
                                 const unsigned long long tw = a.tstat ? wall_clock64() : 0;
                                 ok = wait_flag(a.ready + k * FLAG_STRIDE, (int32_t)a.epoch, a.abort_flag, a.wait_ticks,
-                                               a.status + 2, i, k);
+                                               a.status + 2, i, k, (unsigned int)a.max_pause);
                                 if (a.tstat) st_wait += wall_clock64() - tw;
                             }
                             ok = __shfl(ok, 0, 64);
@@ -677,6 +756,7 @@ __global__ __launch_bounds__(IT) void ilut_row_kernel(IlutDevArgs a) {
                     stop = 1;
                     if (tid == 0) __hip_atomic_store(a.status + 4, (int32_t)(i + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 }
+                if (tid == 0) n_upd += (unsigned long long)(len - 1);
                 if (a.tstat && tid == 0) { st_upd += wall_clock64() - tq; ++st_usteps; st_ent += len; }
             }
             if (stop && fl == -2 && tid == 0)
@@ -695,11 +775,11 @@ __global__ __launch_bounds__(IT) void ilut_row_kernel(IlutDevArgs a) {
             // is written afterwards.
             const int64_t lb0 = a.l_off[i], ub0 = a.u_off[i];
             bool bad = false;
+            double2 dg = make_double2(0.0, 0.0);
+            if (tid == 0 && ((bits[dpos >> 5] >> (dpos & 31)) & 1u)) dg = w[dpos];
             const int nu = output_side(w, bits, dpos + 1, W, lo, tau2, lfil, a.u_col + ub0 + 1, a.u_val + ub0 + 1, true,
                                        &bad, side, hist, sbuf);
             if (tid == 0) {
-                double2 dg = make_double2(0.0, 0.0);
-                if ((bits[dpos >> 5] >> (dpos & 31)) & 1u) dg = w[dpos];
                 if (!isfinite(dg.x) || !isfinite(dg.y)) bad = true;
                 const double fl = 1e-14 * rowinf;
                 const double dmag = sqrt(dg.x * dg.x + dg.y * dg.y);
@@ -721,6 +801,7 @@ __global__ __launch_bounds__(IT) void ilut_row_kernel(IlutDevArgs a) {
                     publish_flag(a.abort_flag, 1);
                 }
             } else {
+                if (a.tstat && tid == 0) { const unsigned long long t = wall_clock64(); st_finu += t - tq; }
                 if (tid == 0) {
                     // the release writes the row back from L2 before the flag
                     publish_flag(a.ready + i * FLAG_STRIDE, (int32_t)a.epoch);
@@ -742,6 +823,7 @@ __global__ __launch_bounds__(IT) void ilut_row_kernel(IlutDevArgs a) {
         i = __builtin_amdgcn_readfirstlane(s_row);
         stop = __builtin_amdgcn_readfirstlane(stop | s_stop);
     }
+    if (tid == 0) atomicAdd(reinterpret_cast<unsigned long long*>(a.status + 38), n_upd);
     if (a.tstat && tid == 0) {
         atomicAdd(a.tstat + 0, st_piv);
         atomicAdd(a.tstat + 1, st_wait);
@@ -751,6 +833,8 @@ __global__ __launch_bounds__(IT) void ilut_row_kernel(IlutDevArgs a) {
         atomicAdd(a.tstat + 5, st_steps);
         atomicAdd(a.tstat + 6, st_usteps);
         atomicAdd(a.tstat + 7, st_ent);
+        atomicAdd(a.tstat + 8, st_finu);
+        for (int k = 0; k < 12; ++k) atomicAdd(a.tstat + 9 + k, side.tph[k]);
     }
 }
 
@@ -813,7 +897,7 @@ om_status ilut_factor_dev(const om_csr* A, int item, double drop_tol, double fil
     OM_TRY(uval.alloc(uoff[n]));
     OM_TRY(ready.alloc((size_t)n * FLAG_STRIDE));
     OM_TRY(udiag.alloc(n));
-    OM_TRY(misc.alloc(64));   // [0] row counter, [1..15] status, [32] abort flag (a line of its own)
+    OM_TRY(misc.alloc(64));   // [0] row counter, [2..17] status, [32] abort flag (a line of its own), [40..41] U-row entries read
     const int64_t wstride = (W + 7) & ~7ll;
     OM_TRY(work.alloc((size_t)G * wstride));
     OM_HIP(hipMemsetAsync(ready.p, 0, ready.bytes(), s));
@@ -832,11 +916,13 @@ om_status ilut_factor_dev(const om_csr* A, int item, double drop_tol, double fil
     a.wait_ticks = (long long)((double)std::max(clk_khz, 1000) * 1000.0 * wait_s);
     a.next_row = misc.p; a.abort_flag = misc.p + 32; a.status = misc.p + 2;
     a.acq_fence = 1;
+    a.max_pause = 32;
+    if (const char* e = getenv("OMSS_ILUT_BACKOFF")) a.max_pause = std::max(1, std::min(1024, atoi(e)));
     if (const char* e = getenv("OMSS_ILUT_FENCE")) a.acq_fence = atoi(e) != 0;
     DevBuf<unsigned long long> tstat;
     a.tstat = nullptr;
     if (getenv("OMSS_ILUT_STATS")) {
-        OM_TRY(tstat.alloc(8));
+        OM_TRY(tstat.alloc(21));
         OM_HIP(hipMemsetAsync(tstat.p, 0, tstat.bytes(), s));
         OM_HIP(hipStreamSynchronize(s));
         a.tstat = tstat.p;
@@ -853,12 +939,14 @@ om_status ilut_factor_dev(const om_csr* A, int item, double drop_tol, double fil
     // rows are handed out dynamically, so the blocks need not be co-resident:
     // an ordinary launch (OMSS_ILUT_COOP=1 selects a cooperative one)
     const char* ce = getenv("OMSS_ILUT_COOP");
+    ProfScope prof("ilut", s, 0.0);
     if (ce && atoi(ce) == 1) {
         OM_HIP(hipLaunchCooperativeKernel((const void*)ilut_row_kernel, dim3(G), dim3(IT), args, 0, s));
     } else {
         hipLaunchKernelGGL(ilut_row_kernel, dim3(G), dim3(IT), 0, s, a);
         OM_HIP(hipGetLastError());
     }
+    prof.stop();
     double next_report = 20.0;
     while (true) {
         const hipError_t q = hipStreamQuery(s);
@@ -879,14 +967,19 @@ om_status ilut_factor_dev(const om_csr* A, int item, double drop_tol, double fil
         fprintf(stderr, "[omss] device ILUT: n %lld, window %lld, %d workgroups, %.3f s\n", (long long)n, (long long)W, G,
                 std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
     if (a.tstat) {
-        unsigned long long h[8];
+        unsigned long long h[21];
         OM_HIP(hipMemcpy(h, a.tstat, sizeof h, hipMemcpyDeviceToHost));
         const double us = 1e6 / ((double)std::max(clk_khz, 1000) * 1000.0);
         const double rows = (double)std::max(1ull, h[4]);
         fprintf(stderr, "[ilut stats] %d workgroups, window %lld: per row %.1f steps (%.1f updating, %.0f entries); "
-                "per row us: pivot steps %.1f (of which waiting %.1f), updates %.1f, dropping and output %.1f\n", G,
-                (long long)W, h[5] / rows, h[6] / rows, h[7] / rows, h[0] * us / rows, h[1] * us / rows,
-                h[2] * us / rows, h[3] * us / rows);
+                "per row us: pivot steps %.1f (of which waiting %.1f), updates %.1f, dropping and output %.1f (U side "
+                "to its publication %.1f)\n", G, (long long)W, h[5] / rows, h[6] / rows, h[7] / rows, h[0] * us / rows,
+                h[1] * us / rows, h[2] * us / rows, h[3] * us / rows, h[8] * us / rows);
+        fprintf(stderr, "[ilut stats] dropping and output per row us (both triangles, staged path): positions %.1f, "
+                "keys %.1f, select %.1f, output %.1f\n", h[9] * us / rows, h[10] * us / rows, h[11] * us / rows,
+                h[12] * us / rows);
+        fprintf(stderr, "[ilut stats] triangle outputs: %llu staged in LDS (%llu capped), %llu from the window\n",
+                h[13], h[20], h[15]);
     }
     if (hs[2] != 0) {
         if (err) *err = "ILUT breakdown: non-finite pivot or entry in row " + std::to_string(hs[2] - 1) +
@@ -923,6 +1016,10 @@ om_status ilut_factor_dev(const om_csr* A, int item, double drop_tol, double fil
         }
     }
     D->repaired = hs[3];
+    // algorithmic bytes: the U-row entries read by the eliminations, row i of
+    // A, and the factor written (4-byte column + 16-byte value per entry)
+    D->upd_entries = (int64_t)((uint64_t)(uint32_t)hs[40] | ((uint64_t)(uint32_t)hs[41] << 32));
+    prof.set_bytes(20.0 * ((double)D->upd_entries + (double)A->nnz + (double)(D->nnz_l + D->nnz_u)));
     return OM_OK;
 }
 

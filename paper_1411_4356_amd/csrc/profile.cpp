@@ -56,10 +56,16 @@ ProfScope::ProfScope(const char* cls, hipStream_t s, double bytes) : cls_(cls), 
     if (a_) (void)hipEventRecord(a_, s_);
 }
 
+void ProfScope::stop() {
+    if (!a_ || !b_ || stopped_) return;
+    (void)hipEventRecord(b_, s_);
+    stopped_ = true;
+}
+
 ProfScope::~ProfScope() {
     if (!a_ || !b_) return;
     std::lock_guard<std::mutex> lk(g_mu);
-    (void)hipEventRecord(b_, s_);
+    if (!stopped_) (void)hipEventRecord(b_, s_);
     Cls& c = g_cls[cls_];
     c.pending.emplace_back(a_, b_);
     c.launches += 1;

@@ -12,6 +12,10 @@ class ProfScope {
 public:
     ProfScope(const char* cls, hipStream_t s, double bytes);
     ~ProfScope();
+    // record the stop event now (the destructor then only books the launch)
+    void stop();
+    // algorithmic bytes known only after the launch
+    void set_bytes(double b) { bytes_ = b; }
     ProfScope(const ProfScope&) = delete;
     ProfScope& operator=(const ProfScope&) = delete;
 
@@ -20,6 +24,7 @@ private:
     hipStream_t s_;
     double bytes_;
     hipEvent_t a_ = nullptr, b_ = nullptr;
+    bool stopped_ = false;
 };
 
 }  // namespace omss
