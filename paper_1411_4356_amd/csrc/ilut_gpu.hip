@@ -304,7 +304,7 @@ __device__ unsigned long long select_kth_lds(const unsigned long long* key, int 
 
 constexpr int CAND_MAX = 6144;   // entries of one triangle staged in LDS for the cap
 
-constexpr int RPT = 8;           // candidates per thread held in registers (strided by the block size)
+constexpr int RPT = 8;          // candidate rounds per group (strided by the block size): all of CAND_MAX
 
 struct SideShared {
     unsigned long long key[CAND_MAX];
@@ -393,14 +393,18 @@ __device__ int output_side(const double2* w, const uint32_t* bits, int p0, int p
         // lanes of a wave touch consecutive LDS words and window entries;
         // rounds go in groups of RPT
         const int rounds = (present + IT - 1) / IT, groups = (rounds + RPT - 1) / RPT;
+        // groups of RPT rounds; the loads of the next group are in flight while
+        // a group is processed (at most 3 groups: CAND_MAX = 3 * RPT * IT)
+        static_assert(CAND_MAX <= 3 * RPT * IT, "staging groups");
         int live = 0;
-        for (int gq = 0; gq < groups; ++gq) {
-            double2 v[RPT];
+        auto load_group = [&](double2 (&v)[RPT], int gq) {
 #pragma unroll
             for (int u = 0; u < RPT; ++u) {
                 const int t = (gq * RPT + u) * IT + tid;
                 if (t < present) v[u] = w[ss.pos[t]];
             }
+        };
+        auto key_group = [&](const double2 (&v)[RPT], int gq) {
 #pragma unroll
             for (int u = 0; u < RPT; ++u) {
                 const int t = (gq * RPT + u) * IT + tid;
@@ -411,6 +415,15 @@ __device__ int output_side(const double2* w, const uint32_t* bits, int p0, int p
                     live += cand;
                 }
             }
+        };
+        {
+            double2 va[RPT], vb[RPT];
+            load_group(va, 0);
+            if (groups > 1) load_group(vb, 1);
+            key_group(va, 0);
+            if (groups > 2) load_group(va, 2);
+            if (groups > 1) key_group(vb, 1);
+            if (groups > 2) key_group(va, 2);
         }
         const int tot = block_sum(live, sbuf);   // (its barriers also order the key writes)
         phase(1);
@@ -448,29 +461,42 @@ __device__ int output_side(const double2* w, const uint32_t* bits, int p0, int p
         // output: ranks of the kept candidates in column order, then the
         // loads and stores of a group (consecutive lanes, consecutive ranks)
         int base = 0;
-        for (int gq = 0; gq < groups; ++gq) {
+        struct OutGroup {
             bool f[RPT];
             int pp[RPT];
+            double2 v[RPT];
+        };
+        auto fetch_group = [&](OutGroup& o, int gq) {
 #pragma unroll
             for (int u = 0; u < RPT; ++u) {
                 const int t = (gq * RPT + u) * IT + tid;
-                f[u] = t < present && ss.key[t] != 0ull;
-                pp[u] = t < present ? (int)ss.pos[t] : 0;
+                o.f[u] = t < present && ss.key[t] != 0ull;
+                o.pp[u] = t < present ? (int)ss.pos[t] : 0;
             }
+#pragma unroll
+            for (int u = 0; u < RPT; ++u)
+                if (o.f[u]) o.v[u] = w[o.pp[u]];
+        };
+        auto store_group = [&](const OutGroup& o) {
             int r[RPT], tg;
-            strided_rank(f, r, &tg, ss);
-            double2 v[RPT];
+            strided_rank(o.f, r, &tg, ss);
 #pragma unroll
             for (int u = 0; u < RPT; ++u)
-                if (f[u]) v[u] = w[pp[u]];
-#pragma unroll
-            for (int u = 0; u < RPT; ++u)
-                if (f[u]) {
-                    if (check_finite && (!isfinite(v[u].x) || !isfinite(v[u].y))) *bad = true;
-                    ocol[base + r[u]] = (int32_t)(lo + pp[u]);
-                    oval[base + r[u]] = v[u];
+                if (o.f[u]) {
+                    if (check_finite && (!isfinite(o.v[u].x) || !isfinite(o.v[u].y))) *bad = true;
+                    ocol[base + r[u]] = (int32_t)(lo + o.pp[u]);
+                    oval[base + r[u]] = o.v[u];
                 }
             base += tg;
+        };
+        {
+            OutGroup oa, ob;
+            fetch_group(oa, 0);
+            if (groups > 1) fetch_group(ob, 1);
+            store_group(oa);
+            if (groups > 2) fetch_group(oa, 2);
+            if (groups > 1) store_group(ob);
+            if (groups > 2) store_group(oa);
         }
         phase(3);
         if (ss.on && tid == 0) ++ss.tph[4];
@@ -552,7 +578,7 @@ __global__ __launch_bounds__(IT, 2) void ilut_row_kernel(IlutDevArgs a) {
     // for unfinished rows, in updates and in the dropping and output; counts
     // of rows, steps, updating steps and updated entries
     unsigned long long st_piv = 0, st_wait = 0, st_upd = 0, st_fin = 0, st_rows = 0, st_steps = 0, st_usteps = 0,
-                       st_ent = 0, st_finu = 0, tq = 0;
+                       st_ent = 0, st_finu = 0, st_pub = 0, tq = 0;
     unsigned long long n_upd = 0;   // U-row entries read by this workgroup's eliminations (thread 0)
     if (tid == 0) {
         side.on = a.tstat != nullptr;
@@ -606,77 +632,115 @@ __global__ __launch_bounds__(IT, 2) void ilut_row_kernel(IlutDevArgs a) {
         while (going) {
             if (a.tstat && tid == 0) tq = wall_clock64();
             if (wave == 0) {
-                int found = -1;
-                for (int base = (kprev + 1) >> 5; base <= ((dpos - 1) >> 5) && found < 0; base += 64) {
-                    const int wi = base + lane;
-                    uint32_t word = 0u;
-                    if (wi <= ((dpos - 1) >> 5) && wi < nwords) {
-                        word = bits[wi];
-                        const int lowb = wi * 32, hib = lowb + 32;
-                        if (kprev + 1 > lowb) word &= ~0u << (kprev + 1 - lowb);       // positions > kprev
-                        if (dpos < hib) word &= (dpos - lowb) >= 32 ? ~0u : ((1u << (dpos - lowb)) - 1u);   // < dpos
-                    }
-                    const unsigned long long bal = __ballot(word != 0u);
-                    if (bal) {
-                        const int l = __ffsll((long long)bal) - 1;
-                        const uint32_t wl = __shfl(word, l, 64);
-                        found = (base + l) * 32 + (__ffs((int)wl) - 1);
-                    }
-                }
-                int flag = 0;
+                // Settle the present columns left of the diagonal in order.  The
+                // columns of one bitmap word whose rows are finished are decided
+                // together (lane = bit): entry, pivot and row data in one round of
+                // loads per lane; multipliers below tau are dropped, which changes
+                // no other entry, so every column up to the first kept multiplier
+                // is settled at once and only that one becomes a step.
+                int found = -1, flag = 0;
                 double mr = 0.0, mi = 0.0;
                 int64_t uoff = 0;
                 int ulen = 0;
-                if (found >= 0 && lo + found < 0) {
-                    flag = -2;   // a column left of 0: the window is corrupt
-                } else if (found >= 0) {
-                    const int64_t k = lo + found;
-                    const double2 x = w[found];
-                    if (x.x != 0.0 || x.y != 0.0) {
-                        bool rdy = k >= rlo && k < rlo + 64 && ((rmask >> (k - rlo)) & 1ull);
-                        if (!rdy) {
-                            rlo = k;
-                            const int64_t r = k + lane;
-                            rmask = __ballot(r < i && ld_flag(a.ready + r * FLAG_STRIDE) == (int32_t)a.epoch);
-                            rdy = rmask & 1ull;
-                            // rows seen finished: their data, read below with ordinary
-                            // loads, must not come from lines cached before
-                            if (rmask && a.acq_fence) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                int kscan = kprev;   // positions <= kscan are settled
+                bool searching = true;
+                while (searching) {
+                    uint32_t wl = 0u;
+                    int wbase = -1;
+                    for (int base = (kscan + 1) >> 5; base <= ((dpos - 1) >> 5); base += 64) {
+                        const int wi = base + lane;
+                        uint32_t word = 0u;
+                        if (wi <= ((dpos - 1) >> 5) && wi < nwords) {
+                            word = bits[wi];
+                            const int lowb = wi * 32, hib = lowb + 32;
+                            if (kscan + 1 > lowb) word &= ~0u << (kscan + 1 - lowb);   // positions > kscan
+                            if (dpos < hib) word &= (dpos - lowb) >= 32 ? ~0u : ((1u << (dpos - lowb)) - 1u);   // < dpos
                         }
-                        if (!rdy) {
-                            int ok = 1;
-                            if (lane == 0) {
-                                const unsigned long long tw = a.tstat ? wall_clock64() : 0;
-                                ok = wait_flag(a.ready + k * FLAG_STRIDE, (int32_t)a.epoch, a.abort_flag, a.wait_ticks,
-                                               a.status + 2, i, k, (unsigned int)a.max_pause);
-                                if (a.tstat) st_wait += wall_clock64() - tw;
-                            }
-                            ok = __shfl(ok, 0, 64);
-                            if (ok) {
-                                rmask |= 1ull;
-                                if (a.acq_fence) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-                            } else {
-                                flag = -1;
-                            }
+                        const unsigned long long bal = __ballot(word != 0u);
+                        if (bal) {
+                            const int l = __ffsll((long long)bal) - 1;
+                            wl = (uint32_t)__shfl((int)word, l, 64);
+                            wbase = (base + l) * 32;
+                            break;
                         }
-                        if (flag == 0) {
-                            // pivot, offset and length of row k in one round of loads
-                            const double2 d = ld_coh(a.udiag + k);
-                            const int64_t uo = a.u_off[k], uo1 = a.u_off[k + 1];
-                            const int ul = ld_flag(a.u_len + k);
-                            const double den = d.x * d.x + d.y * d.y;
-                            mr = (x.x * d.x + x.y * d.y) / den;
-                            mi = (x.y * d.x - x.x * d.y) / den;
-                            if (mr * mr + mi * mi < tau2) {
-                                if (lane == 0) w[found] = make_double2(0.0, 0.0);
-                            } else {
-                                if (lane == 0) w[found] = make_double2(mr, mi);
-                                flag = 1;
-                                uoff = uo;
-                                ulen = ul;
-                                if (ulen < 1 || uoff + ulen > uo1) flag = -2;
-                            }
+                    }
+                    if (wbase < 0) break;   // no column left: the row is eliminated
+                    const int first = __ffs((int)wl) - 1;
+                    const int64_t k0 = lo + wbase + first;
+                    if (k0 < 0) {   // a column left of 0: the window is corrupt
+                        flag = -2;
+                        found = wbase + first;
+                        break;
+                    }
+                    if (!(k0 >= rlo && k0 + 31 < rlo + 64)) {
+                        rlo = k0;
+                        const int64_t r = k0 + lane;
+                        rmask = __ballot(r < i && ld_flag(a.ready + r * FLAG_STRIDE) == (int32_t)a.epoch);
+                        // rows seen finished: their data, read below with ordinary
+                        // loads, must not come from lines cached before
+                        if (rmask && a.acq_fence) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                    }
+                    const bool mem = lane < 32 && ((wl >> lane) & 1u);
+                    const int64_t kl = lo + wbase + lane;
+                    const bool rdyl = mem && kl >= rlo && kl < rlo + 64 && ((rmask >> (kl - rlo)) & 1ull);
+                    const unsigned long long notready = __ballot(mem && !rdyl);
+                    if ((notready >> first) & 1ull) {
+                        // the first column's row is unfinished: wait for it
+                        int ok = 1;
+                        if (lane == 0) {
+                            const unsigned long long tw = a.tstat ? wall_clock64() : 0;
+                            ok = wait_flag(a.ready + k0 * FLAG_STRIDE, (int32_t)a.epoch, a.abort_flag, a.wait_ticks,
+                                           a.status + 2, i, k0, (unsigned int)a.max_pause);
+                            if (a.tstat) st_wait += wall_clock64() - tw;
                         }
+                        ok = __shfl(ok, 0, 64);
+                        if (!ok) {
+                            flag = -1;
+                            found = wbase + first;
+                            break;
+                        }
+                        rmask |= 1ull << (k0 - rlo);
+                        if (a.acq_fence) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                        continue;
+                    }
+                    // columns before the first unfinished row are decided now
+                    const int lim = notready ? __ffsll((long long)notready) - 1 : 64;
+                    const bool elig = mem && lane < lim;
+                    double2 x = make_double2(0.0, 0.0), d = make_double2(1.0, 0.0);
+                    int64_t uo = 0, uo1 = 0;
+                    int ul = 0;
+                    if (elig) {
+                        x = w[wbase + lane];
+                        d = ld_coh(a.udiag + kl);
+                        uo = a.u_off[kl];
+                        uo1 = a.u_off[kl + 1];
+                        ul = ld_flag(a.u_len + kl);
+                    }
+                    const bool nz = elig && (x.x != 0.0 || x.y != 0.0);
+                    double ml = 0.0, nl = 0.0;
+                    bool keep = false;
+                    if (nz) {
+                        const double den = d.x * d.x + d.y * d.y;
+                        ml = (x.x * d.x + x.y * d.y) / den;
+                        nl = (x.y * d.x - x.x * d.y) / den;
+                        keep = !(ml * ml + nl * nl < tau2);
+                    }
+                    const unsigned long long kb = __ballot(keep);
+                    const int fk = kb ? __ffsll((long long)kb) - 1 : 64;
+                    if (nz && lane < fk) w[wbase + lane] = make_double2(0.0, 0.0);   // dropped multipliers
+                    if (kb) {
+                        found = wbase + fk;
+                        mr = __shfl(ml, fk, 64);
+                        mi = __shfl(nl, fk, 64);
+                        uoff = (int64_t)__shfl((long long)uo, fk, 64);
+                        ulen = __shfl(ul, fk, 64);
+                        const int64_t uend = (int64_t)__shfl((long long)uo1, fk, 64);
+                        if (lane == fk) w[found] = make_double2(mr, mi);
+                        flag = 1;
+                        if (ulen < 1 || uoff + ulen > uend) flag = -2;
+                        searching = false;
+                    } else {
+                        kscan = wbase + (lim < 32 ? lim - 1 : 31);
                     }
                 }
                 if (lane == 0) {
@@ -804,7 +868,9 @@ __global__ __launch_bounds__(IT, 2) void ilut_row_kernel(IlutDevArgs a) {
                 if (a.tstat && tid == 0) { const unsigned long long t = wall_clock64(); st_finu += t - tq; }
                 if (tid == 0) {
                     // the release writes the row back from L2 before the flag
+                    const unsigned long long tp = a.tstat ? wall_clock64() : 0;
                     publish_flag(a.ready + i * FLAG_STRIDE, (int32_t)a.epoch);
+                    if (a.tstat) st_pub += wall_clock64() - tp;
                     if ((i & 4095) == 0) __hip_atomic_store(a.host_progress, (int32_t)i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
                 }
                 const int nl = output_side(w, bits, 0, dpos, lo, tau2, lfil, a.l_col + lb0, a.l_val + lb0, false, &bad,
@@ -835,6 +901,7 @@ __global__ __launch_bounds__(IT, 2) void ilut_row_kernel(IlutDevArgs a) {
         atomicAdd(a.tstat + 7, st_ent);
         atomicAdd(a.tstat + 8, st_finu);
         for (int k = 0; k < 12; ++k) atomicAdd(a.tstat + 9 + k, side.tph[k]);
+        atomicAdd(a.tstat + 21, st_pub);
     }
 }
 
@@ -922,7 +989,7 @@ om_status ilut_factor_dev(const om_csr* A, int item, double drop_tol, double fil
     DevBuf<unsigned long long> tstat;
     a.tstat = nullptr;
     if (getenv("OMSS_ILUT_STATS")) {
-        OM_TRY(tstat.alloc(21));
+        OM_TRY(tstat.alloc(22));
         OM_HIP(hipMemsetAsync(tstat.p, 0, tstat.bytes(), s));
         OM_HIP(hipStreamSynchronize(s));
         a.tstat = tstat.p;
@@ -967,7 +1034,7 @@ om_status ilut_factor_dev(const om_csr* A, int item, double drop_tol, double fil
         fprintf(stderr, "[omss] device ILUT: n %lld, window %lld, %d workgroups, %.3f s\n", (long long)n, (long long)W, G,
                 std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
     if (a.tstat) {
-        unsigned long long h[21];
+        unsigned long long h[22];
         OM_HIP(hipMemcpy(h, a.tstat, sizeof h, hipMemcpyDeviceToHost));
         const double us = 1e6 / ((double)std::max(clk_khz, 1000) * 1000.0);
         const double rows = (double)std::max(1ull, h[4]);
@@ -978,8 +1045,8 @@ om_status ilut_factor_dev(const om_csr* A, int item, double drop_tol, double fil
         fprintf(stderr, "[ilut stats] dropping and output per row us (both triangles, staged path): positions %.1f, "
                 "keys %.1f, select %.1f, output %.1f\n", h[9] * us / rows, h[10] * us / rows, h[11] * us / rows,
                 h[12] * us / rows);
-        fprintf(stderr, "[ilut stats] triangle outputs: %llu staged in LDS (%llu capped), %llu from the window\n",
-                h[13], h[20], h[15]);
+        fprintf(stderr, "[ilut stats] triangle outputs: %llu staged in LDS (%llu capped), %llu from the window; "
+                "publication (release) per row %.1f us\n", h[13], h[20], h[15], h[21] * us / rows);
     }
     if (hs[2] != 0) {
         if (err) *err = "ILUT breakdown: non-finite pivot or entry in row " + std::to_string(hs[2] - 1) +
