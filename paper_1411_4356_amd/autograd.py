@@ -83,5 +83,4 @@ class SteadyStateObs(torch.autograd.Function):
         jac = api.param_gradient(B, x, lam)[0]             # [3, 5]: d obs_f / d theta_t
         go = grad_out.detach().to("cpu", torch.float64).numpy()
         vjp = go @ jac
-        ctx.state = None
         return torch.tensor(vjp, dtype=torch.float64, device=grad_out.device), None

@@ -341,6 +341,13 @@ def test_autograd_steady_state_obs_matches_oracle_adjoint():
     assert np.max(np.abs(obs.detach().numpy() - vals) / np.abs(vals)) <= 1e-10
     ref = wts.numpy() @ go
     assert np.max(np.abs(theta.grad.numpy() - ref)) <= 1e-7 * np.abs(ref).max()
+    # the full Jacobian, one backward pass per observable on one retained graph
+    obs = P.SteadyStateObs.apply(theta, cfg)
+    for f in range(3):
+        gsel = torch.zeros(3, dtype=torch.float64)
+        gsel[f] = 1.0
+        row, = torch.autograd.grad(obs, theta, gsel, retain_graph=f < 2)
+        assert np.max(np.abs(row.numpy() - go[f])) <= 1e-7 * np.abs(go[f]).max()
 
 
 @pytest.mark.parametrize("ci", [1, 3])
