@@ -58,6 +58,28 @@ def make_workload(name, fill):
     raise SystemExit(f"unknown workload {name}")
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE runs, calibrated with a plain copy), or None
+    when the summary is missing or the kernel source changed since."""
+    import hashlib
+    import re
+    if kernel != "ilut":
+        return None
+    prof = os.path.join(ROOT, "profiles", "ilut_row_kernel_batch360k_hbm_traffic.md")
+    src = os.path.join(ROOT, "paper_1411_4356_amd", "csrc", "ilut_gpu.hip")
+    try:
+        text = open(prof).read()
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    m_t = re.search(r"ilut_traffic_bytes_per_launch:\s*(\d+)", text)
+    m_s = re.search(r"ilut_source_sha256:\s*([0-9a-f]{64})", text)
+    if not m_t or not m_s or m_s.group(1) != sha:
+        return None
+    return float(m_t.group(1))
+
+
 def profile_query(lib, cls):
     launches, ms, nbytes = C.c_int64(), C.c_double(), C.c_double()
     lib.om_profile_query(cls.encode(), C.byref(launches), C.byref(ms), C.byref(nbytes))
@@ -214,7 +236,8 @@ def main():
                    "fill_factor": opts["fill_factor"], "restart": opts["m"], "tol": opts["tol"]},
         "roofline": {"bound": "hbm", "kernel": names[dom],
                      "achieved": dom_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": (dom_gbs / HBM_PEAK_GBS) if dom_gbs else None, "traffic": None,
+                     "frac": (dom_gbs / HBM_PEAK_GBS) if dom_gbs else None,
+                     "traffic": measured_traffic(dom) if args.workload == "batch360k" and args.fill is None else None,
                      "avg_launch_ms": dom_ms, "launches": q[dom][0],
                      "algorithmic_bytes_per_launch": (q[dom][2] / q[dom][0]) if q[dom][0] else None},
         "kernels": {k: {"GB/s": rate(q[k])[0], "avg_ms": rate(q[k])[1], "launches": q[k][0],
