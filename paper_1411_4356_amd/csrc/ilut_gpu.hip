@@ -306,8 +306,13 @@ constexpr int CAND_MAX = 6144;   // entries of one triangle staged in LDS for th
 
 constexpr int RPT = 8;          // candidate rounds per group (strided by the block size): all of CAND_MAX
 
+// While a row is eliminated, the staging arrays hold the part of the dense
+// working row around the diagonal (WIN_N positions, the most updated ones):
+// its read-modify-writes stay in LDS instead of going to memory.
+constexpr int WIN_N = 3584;
+
 struct SideShared {
-    unsigned long long key[CAND_MAX];
+    alignas(16) unsigned long long key[CAND_MAX];
     uint16_t pos[CAND_MAX];
     int cnt[RPT][IWAVES];        // per round and wave: flags set (scans in candidate order)
     unsigned long long tph[12];  // diagnostics (thread 0): [0..3] ticks in positions, keys, select, output;
@@ -573,6 +578,19 @@ __global__ __launch_bounds__(IT, 2) void ilut_row_kernel(IlutDevArgs a) {
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int W = a.W, nwords = (W + 31) >> 5;
     double2* w = a.work + (int64_t)blockIdx.x * a.wstride;
+    static_assert(WIN_N * sizeof(double2) <= CAND_MAX * (sizeof(unsigned long long) + sizeof(uint16_t)),
+                  "window cache larger than the staging arrays");
+    double2* swin = reinterpret_cast<double2*>(side.key);
+    const int cbase = a.lb - WIN_N / 2;   // window position held at swin[0]
+    auto wget = [&](int p) -> double2 {
+        const unsigned q = (unsigned)(p - cbase);
+        return q < (unsigned)WIN_N ? swin[q] : w[p];
+    };
+    auto wput = [&](int p, double2 v) {
+        const unsigned q = (unsigned)(p - cbase);
+        if (q < (unsigned)WIN_N) swin[q] = v;
+        else w[p] = v;
+    };
 
     // diagnostics (thread 0): ticks in the pivot steps of wave 0, in waits
     // for unfinished rows, in updates and in the dropping and output; counts
@@ -602,7 +620,7 @@ __global__ __launch_bounds__(IT, 2) void ilut_row_kernel(IlutDevArgs a) {
         for (int32_t t = r0 + tid; t < r1; t += IT) {
             const int p = (int)(a.col[t] - lo);
             const double2 v = a.val[t];
-            w[p] = v;
+            wput(p, v);
             atomicOr(&bits[p >> 5], 1u << (p & 31));
             const double m = sqrt(v.x * v.x + v.y * v.y);
             mx = m > mx ? m : mx;
@@ -710,7 +728,7 @@ __global__ __launch_bounds__(IT, 2) void ilut_row_kernel(IlutDevArgs a) {
                     int64_t uo = 0, uo1 = 0;
                     int ul = 0;
                     if (elig) {
-                        x = w[wbase + lane];
+                        x = wget(wbase + lane);
                         d = ld_coh(a.udiag + kl);
                         uo = a.u_off[kl];
                         uo1 = a.u_off[kl + 1];
@@ -727,7 +745,7 @@ __global__ __launch_bounds__(IT, 2) void ilut_row_kernel(IlutDevArgs a) {
                     }
                     const unsigned long long kb = __ballot(keep);
                     const int fk = kb ? __ffsll((long long)kb) - 1 : 64;
-                    if (nz && lane < fk) w[wbase + lane] = make_double2(0.0, 0.0);   // dropped multipliers
+                    if (nz && lane < fk) wput(wbase + lane, make_double2(0.0, 0.0));   // dropped multipliers
                     if (kb) {
                         found = wbase + fk;
                         mr = __shfl(ml, fk, 64);
@@ -735,7 +753,7 @@ __global__ __launch_bounds__(IT, 2) void ilut_row_kernel(IlutDevArgs a) {
                         uoff = (int64_t)__shfl((long long)uo, fk, 64);
                         ulen = __shfl(ul, fk, 64);
                         const int64_t uend = (int64_t)__shfl((long long)uo1, fk, 64);
-                        if (lane == fk) w[found] = make_double2(mr, mi);
+                        if (lane == fk) wput(found, make_double2(mr, mi));
                         flag = 1;
                         if (ulen < 1 || uoff + ulen > uend) flag = -2;
                         searching = false;
@@ -792,7 +810,7 @@ __global__ __launch_bounds__(IT, 2) void ilut_row_kernel(IlutDevArgs a) {
                             } else {
                                 pc[j] = p;
                                 have[j] = (bits[p >> 5] >> (p & 31)) & 1u;
-                                if (have[j]) wv[j] = w[p];
+                                if (have[j]) wv[j] = wget(p);
                             }
                         } else {
                             pc[j] = -1;
@@ -808,9 +826,9 @@ __global__ __launch_bounds__(IT, 2) void ilut_row_kernel(IlutDevArgs a) {
                             double2 c = wv[j];
                             c.x -= pr;
                             c.y -= pi;
-                            w[p] = c;
+                            wput(p, c);
                         } else {
-                            w[p] = make_double2(-pr, -pi);
+                            wput(p, make_double2(-pr, -pi));
                             atomicOr(&bits[p >> 5], 1u << (p & 31));
                         }
                     }
@@ -837,6 +855,12 @@ __global__ __launch_bounds__(IT, 2) void ilut_row_kernel(IlutDevArgs a) {
             // 3. dropping, cap, output.  The U row and the pivot come first and
             // are published at once (later rows wait only for them); the L row
             // is written afterwards.
+            // the part of the working row held in LDS goes back to the window
+            for (int q = tid; q < WIN_N; q += IT) {
+                const int pp = cbase + q;
+                if (pp >= 0 && pp < W && ((bits[pp >> 5] >> (pp & 31)) & 1u)) w[pp] = swin[q];
+            }
+            __syncthreads();
             const int64_t lb0 = a.l_off[i], ub0 = a.u_off[i];
             bool bad = false;
             double2 dg = make_double2(0.0, 0.0);
