@@ -782,12 +782,11 @@ __global__ __launch_bounds__(IT, 2) void ilut_row_kernel(IlutDevArgs a) {
                 const int64_t ub0 = s_uoff[par];
                 const int len = __builtin_amdgcn_readfirstlane(s_ulen[par]);
                 bool badcol = false;
-                // UF entries per thread at a time: all their loads are issued
-                // before any is used (the columns of a U row are distinct, so
-                // the updates of one step never meet)
-                for (int q0 = 1 + tid; q0 < len; q0 += IT * UF) {
-                    int pc[UF];
-                    double2 uv[UF];
+                // UF entries per thread at a time (the columns of a U row are
+                // distinct, so the updates of one step never meet); the U-row
+                // loads of the next round are issued before a round's window
+                // entries are read, so the two latencies overlap
+                auto load_u = [&](int q0, int (&pc)[UF], double2 (&uv)[UF]) {
 #pragma unroll
                     for (int j = 0; j < UF; ++j) {
                         const int q = q0 + j * IT;
@@ -797,6 +796,8 @@ __global__ __launch_bounds__(IT, 2) void ilut_row_kernel(IlutDevArgs a) {
                             uv[j] = a.u_val[ub0 + q];
                         }
                     }
+                };
+                auto update = [&](int q0, int (&pc)[UF], const double2 (&uv)[UF]) {
                     bool have[UF];
                     double2 wv[UF];
 #pragma unroll
@@ -830,6 +831,20 @@ __global__ __launch_bounds__(IT, 2) void ilut_row_kernel(IlutDevArgs a) {
                         } else {
                             wput(p, make_double2(-pr, -pi));
                             atomicOr(&bits[p >> 5], 1u << (p & 31));
+                        }
+                    }
+                };
+                {
+                    constexpr int RS = IT * UF;   // entries per round
+                    int pca[UF], pcb[UF];
+                    double2 uva[UF], uvb[UF];
+                    load_u(1 + tid, pca, uva);
+                    for (int q0 = 1 + tid; q0 < len; q0 += 2 * RS) {
+                        if (q0 + RS < len) load_u(q0 + RS, pcb, uvb);
+                        update(q0, pca, uva);
+                        if (q0 + RS < len) {
+                            if (q0 + 2 * RS < len) load_u(q0 + 2 * RS, pca, uva);
+                            update(q0 + RS, pcb, uvb);
                         }
                     }
                 }
