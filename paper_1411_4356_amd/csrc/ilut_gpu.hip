@@ -643,6 +643,7 @@ __global__ __launch_bounds__(IT, 2) void ilut_row_kernel(IlutDevArgs a) {
         // multiplier) and publishes it in a parity-indexed slot; the other waves
         // read the slot after the barrier, so two steps never share one.
         int kprev = -1;
+        bool badrow = false;   // a U-row column outside the window was met
         int64_t rlo = -(1ll << 40);     // wave 0: rows rlo..rlo+63 whose flags are cached in rmask
         unsigned long long rmask = 0ull;
         int par = 0;
@@ -848,11 +849,7 @@ __global__ __launch_bounds__(IT, 2) void ilut_row_kernel(IlutDevArgs a) {
                         }
                     }
                 }
-                if (block_or(badcol, s_or)) {
-                    going = 0;
-                    stop = 1;
-                    if (tid == 0) __hip_atomic_store(a.status + 4, (int32_t)(i + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                }
+                badrow |= badcol;   // checked once the row is eliminated (bad columns are skipped)
                 if (tid == 0) n_upd += (unsigned long long)(len - 1);
                 if (a.tstat && tid == 0) { st_upd += wall_clock64() - tq; ++st_usteps; st_ent += len; }
             }
@@ -862,6 +859,10 @@ __global__ __launch_bounds__(IT, 2) void ilut_row_kernel(IlutDevArgs a) {
             par ^= 1;
             going = __builtin_amdgcn_readfirstlane(going);
             stop = __builtin_amdgcn_readfirstlane(stop);
+        }
+        if (block_or(badrow, s_or)) {
+            stop = 1;
+            if (tid == 0) __hip_atomic_store(a.status + 4, (int32_t)(i + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         if (a.tstat && tid == 0) tq = wall_clock64();
         if (stop) {
