@@ -45,6 +45,8 @@ static om_status finish_views(om_ilu* M, hipStream_t s) {
     OM_TRY(M->scratch.progress.alloc(B));
     OM_TRY(M->scratch.abort_flag.alloc(1));
     OM_HIP(hipMemsetAsync(M->scratch.fdone.p, 0, M->scratch.fdone.bytes(), s));
+    // far sums start unwritten (all bits set; see trsv.hip)
+    OM_HIP(hipMemsetAsync(M->scratch.far_buf.p, 0xff, M->scratch.far_buf.bytes(), s));
     OM_HIP(hipMemsetAsync(M->scratch.progress.p, 0, M->scratch.progress.bytes(), s));
     OM_HIP(hipMemsetAsync(M->scratch.abort_flag.p, 0, M->scratch.abort_flag.bytes(), s));
     M->scratch.epoch = 0;

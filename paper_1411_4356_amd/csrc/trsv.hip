@@ -106,6 +106,27 @@ __device__ __forceinline__ VT sweep(VT r, const VT* tri, int lane) {
     return r;
 }
 
+// An unwritten far sum has every bit set.  A far sum counts as written only
+// when none of its 32-bit words is all ones: a store seen in part then reads
+// as unwritten, and a written value that happens to hold such a word costs a
+// wait for the flag, never a wrong result.
+template <typename VT> __device__ inline bool is_unwritten(VT v);
+template <> __device__ inline bool is_unwritten<double2>(double2 v) {
+    const unsigned long long a = (unsigned long long)__double_as_longlong(v.x);
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v.y);
+    return (unsigned)a == ~0u || (unsigned)(a >> 32) == ~0u || (unsigned)b == ~0u || (unsigned)(b >> 32) == ~0u;
+}
+template <> __device__ inline bool is_unwritten<float2>(float2 v) {
+    return __float_as_int(v.x) == -1 || __float_as_int(v.y) == -1;
+}
+template <typename VT> __device__ inline VT unwritten();
+template <> __device__ inline double2 unwritten<double2>() {
+    return make_double2(__longlong_as_double(-1ll), __longlong_as_double(-1ll));
+}
+template <> __device__ inline float2 unwritten<float2>() {
+    return make_float2(__int_as_float(-1), __int_as_float(-1));
+}
+
 // coherent (agent-scope) loads and write-through stores of complex values
 template <typename VT> __device__ inline VT ld_coh(const VT* p);
 template <> __device__ inline double2 ld_coh<double2>(const double2* p) {
@@ -431,12 +452,16 @@ __global__ __launch_bounds__(64 * TW) void trsv_coop_kernel(const TriView<VT>* _
 #pragma unroll
         for (int j = 0; j < MPW; ++j) { mc[j] = 0; mv[j] = czero<VT>(); }
         const int64_t m0 = g1 < S.nblk ? ldc(S.mid_off + g1) : 0, m1 = g1 < S.nblk ? ldc(S.mid_off + g1 + 1) : 0;
+        VT fb = czero<VT>();
         if (wave == 0) {
             const int64_t row = g * 64 + lane;
             if (row < n) {
                 r0 = ldg(y + (S.rev ? (n - 1 - row) : row));
                 if (S.dinv) dv = ldg(S.dinv + row);
             }
+            // the helpers' far sum of block g, read now: if it is already
+            // written, neither the flag nor a second read is on the chain
+            fb = ld_coh(far_buf + g * 64 + lane);
         } else {
             if (m1 > m0) {
                 // slots past the end repeat the last one (not accumulated)
@@ -485,7 +510,6 @@ __global__ __launch_bounds__(64 * TW) void trsv_coop_kernel(const TriView<VT>* _
             }
         }
         s_part[wave][lane] = acc;
-        VT fb = czero<VT>();
         if (wave == 0) {
             // publish block g-1: its unknowns were stored at the end of the
             // previous iteration, and waiting for them here rather than there
@@ -496,13 +520,13 @@ __global__ __launch_bounds__(64 * TW) void trsv_coop_kernel(const TriView<VT>* _
                 if (lane == 0) __hip_atomic_store(progress, ep + g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 if (a.tstat && lane == 0) t_pub += wall_clock64() - tP;
             }
-            if (lane == 0) {
-                const unsigned long long tB = a.tstat ? wall_clock64() : 0;
-                if (!wait_eq32(fdone + g, (int32_t)a.epoch, a.abort_flag)) s_fail = 1;
-                if (a.tstat) { const unsigned long long tC = wall_clock64(); t_near += tB - tA; t_wait += tC - tB; tA = tC; }
+            const unsigned long long tB = a.tstat ? wall_clock64() : 0;
+            if (__ballot(is_unwritten(fb)) != 0ull) {
+                // not yet (or only partly) written: wait for the flag, then read again
+                if (lane == 0 && !wait_eq32(fdone + g, (int32_t)a.epoch, a.abort_flag)) s_fail = 1;
+                fb = ld_coh(far_buf + g * 64 + lane);
             }
-            // the helpers' far sum of block g (published before the flag)
-            fb = ld_coh(far_buf + g * 64 + lane);
+            if (a.tstat && lane == 0) { const unsigned long long tC = wall_clock64(); t_near += tB - tA; t_wait += tC - tB; tA = tC; }
         }
         __syncthreads();
         if (__builtin_amdgcn_readfirstlane(s_fail)) return;
@@ -519,6 +543,8 @@ __global__ __launch_bounds__(64 * TW) void trsv_coop_kernel(const TriView<VT>* _
             r = sweep(r, s_tri[buf], lane);
             s_ring[(g * 64 + lane) & (RING - 1)] = r;
             if (valid) st_wt(x + (S.rev ? (n - 1 - row) : row), r);
+            // consumed: marked unwritten for the next solve
+            st_wt(far_buf + g * 64 + lane, unwritten<VT>());
             if (a.tstat && lane == 0) { const unsigned long long tD = wall_clock64(); t_sweep += tD - tA; tA = tD; }
         } else if (g1 < S.nblk) {
             // waves 1-3: stage the near list of block g+1 (copies straight to
@@ -995,6 +1021,8 @@ om_status trsv_check(const om_ilu* Mc, hipStream_t s) {
     OM_HIP(hipStreamSynchronize(s));
     if (f) {
         OM_HIP(hipMemsetAsync(M->scratch.abort_flag.p, 0, sizeof f, s));
+        // an abandoned solve may leave far sums written but not consumed
+        OM_HIP(hipMemsetAsync(M->scratch.far_buf.p, 0xff, M->scratch.far_buf.bytes(), s));
         OM_HIP(hipStreamSynchronize(s));
         set_error("a triangular solve timed out waiting for its helpers (abort flag set)");
         return OM_ETIMEOUT;
