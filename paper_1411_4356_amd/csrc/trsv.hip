@@ -48,6 +48,7 @@ __device__ inline float bcast(float v, int l) {
 
 constexpr int TW = 4;              // waves per workgroup
 constexpr int TRI_N = 2016;        // packed strictly-lower 64x64
+constexpr int TRI_LD = TRI_N + 1;  // a triangle in LDS: the packed entries, then a zero
 constexpr int RING = NEAR_BLOCKS * 64;
 constexpr int NEAR_PF = 64;        // near slots of the next block staged in LDS (all: a row has at most 64 entries in the previous block)
 constexpr int NXCD = 8;
@@ -59,14 +60,17 @@ constexpr long long SPIN_LIMIT = 1ll << 22;
 // hand side of lane = row on entry and the unknown on exit.  Columns are
 // taken in chunks of SWC: the LDS entries of chunk k+1 are requested before
 // the steps of chunk k (scheduling barriers keep that order), so that the
-// chain of dependent steps does not wait for LDS.
+// chain of dependent steps does not wait for LDS.  Lanes at or above the
+// diagonal of a column read the zero after the packed entries (tri[TRI_N]):
+// their update subtracts zero, so every step runs on all lanes, without a
+// lane mask on the chain.
 constexpr int SWC = 8;
 template <typename VT>
 __device__ __forceinline__ void sweep_load(VT (&t)[SWC], const VT* tri, int c0, int lane) {
 #pragma unroll
     for (int j = 0; j < SWC; ++j) {
         const int c = c0 + j;
-        if (c < 63) t[j] = tri[c * 63 - (c * (c - 1)) / 2 + (lane > c ? lane - c - 1 : 0)];
+        if (c < 63) t[j] = tri[lane > c ? c * 63 - (c * (c - 1)) / 2 + lane - c - 1 : TRI_N];
     }
 }
 template <int K, typename VT>
@@ -81,12 +85,10 @@ __device__ __forceinline__ void sweep_chunk(VT& r, const VT (&cur)[SWC], VT (&nx
             const VT t = cur[j];
             const ST xr = bcast(r.x, c);
             const ST xi = bcast(r.y, c);
-            if (lane > c) {
-                r.x -= t.x * xr;
-                r.x += t.y * xi;
-                r.y -= t.x * xi;
-                r.y -= t.y * xr;
-            }
+            r.x -= t.x * xr;
+            r.x += t.y * xi;
+            r.y -= t.x * xi;
+            r.y -= t.y * xr;
         }
     }
     __builtin_amdgcn_sched_barrier(0);
@@ -164,7 +166,8 @@ __global__ __launch_bounds__(64 * TW) void trsv_chain_kernel(const TriView<VT>* 
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     __shared__ VT part[TW][64];
-    __shared__ VT tri[TRI_N];
+    __shared__ VT tri[TRI_LD];
+    if (threadIdx.x == 0) tri[TRI_N] = czero<VT>();   // (ordered by the first barrier below)
 
     for (int64_t g = 0; g < S.nblk; ++g) {
         {
@@ -348,7 +351,7 @@ __global__ __launch_bounds__(64 * TW) void trsv_coop_kernel(const TriView<VT>* _
     const int64_t ep = (int64_t)a.epoch << 32;
     // LDS of the critical workgroup, as separate objects: the compiler then
     // knows that reads of one do not depend on copies still landing in another
-    __shared__ __attribute__((aligned(16))) VT s_tri[2][TRI_N];
+    __shared__ __attribute__((aligned(16))) VT s_tri[2][TRI_LD];
     __shared__ __attribute__((aligned(16))) VT s_near_v[NEAR_PF][64];
     __shared__ __attribute__((aligned(16))) int32_t s_near_c[NEAR_PF][64];
     __shared__ VT s_part[TW][64];
@@ -435,6 +438,8 @@ __global__ __launch_bounds__(64 * TW) void trsv_coop_kernel(const TriView<VT>* _
     if (wave > 0) s_mid[0][wave - 1][lane] = czero<VT>();
     if (threadIdx.x == 0) {
         s_fail = 0;
+        s_tri[0][TRI_N] = czero<VT>();
+        s_tri[1][TRI_N] = czero<VT>();
         __hip_atomic_store(progress, ep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     __syncthreads();
@@ -611,7 +616,7 @@ template <typename VT>
 struct MrhsShared {
     union {
         struct {
-            VT tri[2][TRI_N];
+            VT tri[2][TRI_LD];
             VT near_v[NEAR_PF][64];
             uint8_t near_c[NEAR_PF][64];   // column within the previous block
             VT ring[RING][MAXB];
@@ -756,6 +761,8 @@ __global__ __launch_bounds__(MT) void trsv_mrhs_kernel(const TriView<VT>* __rest
     nv0 = nv1 = nv2 = nv3 = nv4 = nv5 = nv6 = nv7 = czero<VT>();
     if (threadIdx.x == 0) {
         sh.fail = 0;
+        sh.cw.tri[0][TRI_N] = czero<VT>();
+        sh.cw.tri[1][TRI_N] = czero<VT>();
         __hip_atomic_store(a.progress, ep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     unsigned long long t_wait = 0, t_all = 0;

@@ -313,6 +313,27 @@ def test_device_ilut_is_the_host_factor_bit_for_bit(ci, monkeypatch):
     assert np.array_equal(_bits(L2.data), _bits(Lg.data)) and np.array_equal(_bits(U2.data), _bits(Ug.data))
 
 
+@pytest.mark.parametrize("stage", ["8,8128", "0,0", "48,300"])
+@pytest.mark.parametrize("ci", [3, 6])
+def test_device_ilut_staging_paths_give_the_host_factor(ci, stage, monkeypatch):
+    """The dropping and cap of a triangle (Sec. II) stage its keys in LDS
+    compactly (few present entries), densely (a key per window position) or
+    not at all (keys re-read from the working row).  The limits are lowered
+    here so that small operators take every path: the factor is the host's,
+    bit for bit, whichever path each row took."""
+    p, d, fill = ILUT_CASES[ci]
+    A, _ = P.liouvillian_build(p)
+    B, perm, _ = P.rcm_permute(A)
+    monkeypatch.setenv("OMSS_ILUT", "device")
+    monkeypatch.setenv("OMSS_ILUT_STAGE", stage)
+    M = P.ilu_factor(B, d, fill, keep_host=True)
+    Lg, Ug = M.export(0)
+    Lh, Uh, _ = P.host_ilut(B.to_scipy(), d, fill)
+    for X, Y in ((Lg, Lh), (Ug, Uh)):
+        assert np.array_equal(X.indptr, Y.indptr) and np.array_equal(X.indices, Y.indices)
+        assert np.array_equal(_bits(X.data), _bits(Y.data))
+
+
 def test_device_ilut_batch_items_are_factored_independently(monkeypatch):
     monkeypatch.setenv("OMSS_ILUT", "device")
     ps = [W.TINY.replace(nc=4, nm=9, E=e) for e in (0.15, 0.45, 0.3)]
