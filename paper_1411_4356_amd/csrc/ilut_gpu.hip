@@ -79,6 +79,7 @@ struct IlutDevArgs {
     unsigned long long* tstat;  // diagnostics (nullable): wall-clock ticks and counts per phase
     int32_t acq_fence;      // agent-scope acquire fence after observing finished rows
     int32_t max_pause;      // longest back-off of a wait, in units of s_sleep(1)
+    int32_t cand_lim;       // largest LDS staging used (<= CAND_MAX; smaller only to exercise the other path)
     int32_t* status;        // [0] first breakdown row + 1 (0 = none), [1] repaired pivots, [38..39] U-row entries read,
                             // [2], [3] row + 1 of the waiter and of the awaited row on a timeout,
                             // [4] row + 1 that found inconsistent row data
@@ -359,7 +360,7 @@ __device__ inline void strided_rank(const bool (&f)[RPT], int (&r)[RPT], int* to
 // entries reads its keys from the window in every pass instead.
 __device__ int output_side(const double2* w, const uint32_t* bits, int p0, int p1, int64_t lo, double tau2, int lfil,
                            int32_t* ocol, double2* oval, bool check_finite, bool* bad, SideShared& ss,
-                           unsigned int* hist, int* sbuf) {
+                           unsigned int* hist, int* sbuf, int cand_lim) {
     const int tid = threadIdx.x;
     // present positions per thread over a contiguous range of bitmap words
     const int wlo = p0 >> 5, whi = p1 > p0 ? ((p1 - 1) >> 5) + 1 : wlo;
@@ -380,7 +381,7 @@ __device__ int output_side(const double2* w, const uint32_t* bits, int p0, int p
     for (int q = q0; q < q1; ++q) mine += __popc(word_at(q));
     int present;
     const int off = block_scan(mine, &present, sbuf);
-    if (present <= CAND_MAX) {
+    if (present <= cand_lim) {
         {
             int j = off;
             for (int q = q0; q < q1; ++q) {
@@ -882,7 +883,7 @@ __global__ __launch_bounds__(IT, 2) void ilut_row_kernel(IlutDevArgs a) {
             double2 dg = make_double2(0.0, 0.0);
             if (tid == 0 && ((bits[dpos >> 5] >> (dpos & 31)) & 1u)) dg = w[dpos];
             const int nu = output_side(w, bits, dpos + 1, W, lo, tau2, lfil, a.u_col + ub0 + 1, a.u_val + ub0 + 1, true,
-                                       &bad, side, hist, sbuf);
+                                       &bad, side, hist, sbuf, a.cand_lim);
             if (tid == 0) {
                 if (!isfinite(dg.x) || !isfinite(dg.y)) bad = true;
                 const double fl = 1e-14 * rowinf;
@@ -914,7 +915,7 @@ __global__ __launch_bounds__(IT, 2) void ilut_row_kernel(IlutDevArgs a) {
                     if ((i & 4095) == 0) __hip_atomic_store(a.host_progress, (int32_t)i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
                 }
                 const int nl = output_side(w, bits, 0, dpos, lo, tau2, lfil, a.l_col + lb0, a.l_val + lb0, false, &bad,
-                                           side, hist, sbuf);
+                                           side, hist, sbuf, a.cand_lim);
                 if (tid == 0) a.l_len[i] = nl;
             }
         }
@@ -1026,6 +1027,11 @@ om_status ilut_factor_dev(const om_csr* A, int item, double drop_tol, double fil
     a.max_pause = 32;
     if (const char* e = getenv("OMSS_ILUT_BACKOFF")) a.max_pause = std::max(1, std::min(1024, atoi(e)));
     if (const char* e = getenv("OMSS_ILUT_FENCE")) a.acq_fence = atoi(e) != 0;
+    // OMSS_ILUT_STAGE=c: a lower limit of the LDS staging of the dropping (the
+    // factor does not depend on it; tests use small limits so that small
+    // operators also take the path that reads the keys from the working row)
+    a.cand_lim = CAND_MAX;
+    if (const char* e = getenv("OMSS_ILUT_STAGE")) a.cand_lim = std::max(0, std::min(CAND_MAX, atoi(e)));
     DevBuf<unsigned long long> tstat;
     a.tstat = nullptr;
     if (getenv("OMSS_ILUT_STATS")) {

@@ -313,14 +313,14 @@ def test_device_ilut_is_the_host_factor_bit_for_bit(ci, monkeypatch):
     assert np.array_equal(_bits(L2.data), _bits(Lg.data)) and np.array_equal(_bits(U2.data), _bits(Ug.data))
 
 
-@pytest.mark.parametrize("stage", ["8,8128", "0,0", "48,300"])
+@pytest.mark.parametrize("stage", ["0", "48"])
 @pytest.mark.parametrize("ci", [3, 6])
 def test_device_ilut_staging_paths_give_the_host_factor(ci, stage, monkeypatch):
-    """The dropping and cap of a triangle (Sec. II) stage its keys in LDS
-    compactly (few present entries), densely (a key per window position) or
-    not at all (keys re-read from the working row).  The limits are lowered
-    here so that small operators take every path: the factor is the host's,
-    bit for bit, whichever path each row took."""
+    """The dropping and cap of a triangle (Sec. II) stage its keys in LDS when
+    few entries are present and otherwise re-read them from the working row
+    in every digit pass.  The staging limit is lowered here (0: no triangle
+    staged; 48: a mix) so that small operators take the second path too: the
+    factor is the host's, bit for bit, whichever path each row took."""
     p, d, fill = ILUT_CASES[ci]
     A, _ = P.liouvillian_build(p)
     B, perm, _ = P.rcm_permute(A)
