@@ -154,16 +154,28 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison step")
     ap.add_argument("--cpu-budget", type=float, default=30.0)
     ap.add_argument("--quiet", action="store_true", help="no library progress lines on stderr")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run three plain device copies of 1 GiB (the reference dispatches that scale the "
+                         "FETCH_SIZE / WRITE_SIZE byte counters) and exit")
     args = ap.parse_args()
     if not args.quiet:
         os.environ["OMSS_VERBOSE"] = "1"
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "
-              "(no multi-GPU path: the batch items would shard one per GPU, see the design notes).",
-              file=sys.stderr)
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (there is no multi-GPU "
+              "path; the batch items would shard one or more per GPU).", file=sys.stderr)
         sys.exit(2)
 
     import torch
+
+    if args.copy_calibration:
+        a = torch.ones(2 ** 28, dtype=torch.float32, device="cuda")   # 1 GiB
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log("copied 3 x 1 GiB")
+        return
 
     import paper_1411_4356_amd as P
     lib = P.lib()
