@@ -435,16 +435,21 @@ __device__ int output_side(const double2* w, const uint32_t* bits, int p0, int p
         phase(1);
         const bool cap = tot > lfil;
         if (ss.on && tid == 0) ss.tph[11] += cap;
+        unsigned long long thr = 0ull;   // a candidate is kept when its key exceeds thr (dropped keys are 0)
         if (cap) {
             int n_gt = 0;
             // lfil = 0 keeps nothing: K above every key, no ties taken
             const unsigned long long K = lfil > 0 ? select_kth_lds(ss.key, present, lfil, &n_gt, hist, sbuf + 4) : ~0ull;
             phase(2);
-            // ties at K: the first (lfil - n_gt) in column order are kept; the
-            // keys are replaced by the decision (1 kept, 0 not)
             const int take = lfil - n_gt;
+            // take = 0 (the usual case: the select ends where the lfil-th and
+            // the next key fall in different digit ranges): the kept keys are
+            // exactly those above K.  Otherwise the first `take` ties at K in
+            // column order are kept, and the keys are replaced by the
+            // decision (1 kept, 0 not).
+            if (take <= 0) thr = K;
             int base = 0;
-            for (int gq = 0; gq < groups; ++gq) {
+            for (int gq = 0; gq < (take > 0 ? groups : 0); ++gq) {
                 bool f[RPT];
                 unsigned long long kk[RPT];
 #pragma unroll
@@ -476,7 +481,7 @@ __device__ int output_side(const double2* w, const uint32_t* bits, int p0, int p
 #pragma unroll
             for (int u = 0; u < RPT; ++u) {
                 const int t = (gq * RPT + u) * IT + tid;
-                o.f[u] = t < present && ss.key[t] != 0ull;
+                o.f[u] = t < present && ss.key[t] > thr;
                 o.pp[u] = t < present ? (int)ss.pos[t] : 0;
             }
 #pragma unroll
