@@ -229,6 +229,21 @@ om_status ilu_apply(const om_ilu* M, int32_t adjoint, int32_t dtype, const void*
 om_status csr_spmv(const om_csr* A, int32_t adjoint, int32_t dtype, const void* x, void* y,
                    void* stream);
 
+/* ---- liouvillian_apply ----------------------------------------------------
+ * y = A x for every batch item without reading A's stored entries: A must be
+ * a matrix built by liouvillian_build (possibly permuted by rcm_permute), and
+ * each row's entries are re-evaluated from its model parameters (Eq. (3) in
+ * the Fock basis with column-stacked rho, Eq. (4), and the trace row of
+ * Eq. (5) as A was built with).  The values are those liouvillian_build
+ * stores, so y equals csr_spmv(A, 0, ...) up to the order of the additions;
+ * only x, y and the permutation cross memory.  dtype OM_C128 or OM_C64
+ * (values rounded to complex64 as OM_BUILD_C64 stores them; no complex64 copy
+ * of A is needed).  x and y: device arrays of batch*n complex values, not
+ * aliased.  Errors: OM_EINVAL if A carries no model description or for a bad
+ * dtype or aliasing.  With OMSS_SPMV=stencil in the environment the solver's
+ * own products with A (not A^H) use this path too. */
+om_status liouvillian_apply(const om_csr* A, int32_t dtype, const void* x, void* y, void* stream);
+
 /* ---- gmres_solve ----------------------------------------------------------
  * Restarted GMRES(m) with right preconditioning M (nullable = none) on every
  * batch item: solves A x = b (adjoint = 0) or A^H x = b (adjoint = 1) to the

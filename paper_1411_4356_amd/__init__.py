@@ -9,6 +9,7 @@ marshals arguments.
 """
 from ._lib import LibraryMissing, OmError, lib  # noqa: F401
 from .api import (Csr, GmresOpts, Ilu, csr_permute, csr_spmv, gmres_solve, host_ilut, host_rcm,  # noqa: F401
-                  ilu_apply, ilu_factor, liouvillian_build, objective_vectors, observables, param_gradient,
+                  ilu_apply, ilu_factor, liouvillian_apply, liouvillian_build, objective_vectors, observables,
+                  param_gradient,
                   rcm_permute, steady_state)
 from .autograd import SolveConfig, SteadyStateObs  # noqa: F401,E402

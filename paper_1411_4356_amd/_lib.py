@@ -83,6 +83,7 @@ SIGNATURES = {
     "om_ilu_export": (C.c_int, [_P, _i32, _pi64, _pi32, _dp, _pi64, _pi32, _dp]),
     "ilu_apply": (C.c_int, [_P, _i32, _i32, _P, _P, _P]),
     "csr_spmv": (C.c_int, [_P, _i32, _i32, _P, _P, _P]),
+    "liouvillian_apply": (C.c_int, [_P, _i32, _P, _P, _P]),
     "gmres_solve": (C.c_int, [_P, _P, _i32, _P, _P, C.POINTER(om_gmres_opts), C.POINTER(om_gmres_info), _P]),
     "steady_state": (C.c_int, [C.POINTER(om_params), _i32, C.POINTER(om_ss_opts), _P, C.POINTER(om_ss_info),
                                C.POINTER(om_ss_results), _P]),

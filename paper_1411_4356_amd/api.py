@@ -169,6 +169,16 @@ def csr_spmv(A: Csr, x: torch.Tensor, y: torch.Tensor | None = None, adjoint: bo
     return y
 
 
+def liouvillian_apply(A: Csr, x: torch.Tensor, y: torch.Tensor | None = None, stream=None):
+    """y = A x evaluated matrix-free from A's model parameters (no stored
+    entry is read); A comes from liouvillian_build, possibly permuted."""
+    _check_dev(x, (torch.complex128, torch.complex64))
+    y = torch.empty_like(x) if y is None else y
+    dtype = L.OM_C64 if x.dtype == torch.complex64 else L.OM_C128
+    check(lib().liouvillian_apply(A.h, dtype, _ptr(x), _ptr(y), _stream(stream)))
+    return y
+
+
 @dataclass
 class GmresOpts:
     m: int = 50

@@ -249,6 +249,18 @@ om_status csr_spmv(const om_csr* A, int32_t adjoint, int32_t dtype, const void* 
     });
 }
 
+om_status liouvillian_apply(const om_csr* A, int32_t dtype, const void* x, void* y, void* stream) {
+    return guarded([&]() -> om_status {
+        if (!A || !x || !y) { set_error("null argument"); return OM_EINVAL; }
+        if (x == y) { set_error("x and y must not alias"); return OM_EINVAL; }
+        hipStream_t s = as_stream(stream);
+        if (dtype == OM_C128) return lapply<double2>(A, (const double2*)x, (double2*)y, nullptr, s);
+        if (dtype == OM_C64) return lapply<float2>(A, (const float2*)x, (float2*)y, nullptr, s);
+        set_error("bad dtype");
+        return OM_EINVAL;
+    });
+}
+
 om_status gmres_solve(const om_csr* A, const om_ilu* M, int32_t adjoint, const void* b, void* x,
                       const om_gmres_opts* opts, om_gmres_info* info, void* stream) {
     return guarded([&]() -> om_status {

@@ -29,6 +29,13 @@ om_status residual(const om_csr* A, int adjoint, const VT* b, const VT* x, VT* r
                    const int32_t* active, hipStream_t s, const int32_t* act_host = nullptr);
 double spmv_bytes(const om_csr* A, size_t s, const int32_t* act_host);
 
+// lapply.hip: y = A x from the model's stencil (A built by liouvillian_build,
+// possibly permuted); no stored entry is read
+template <typename VT>
+om_status lapply(const om_csr* A, const VT* x, VT* y, const int32_t* active, hipStream_t s,
+                 const int32_t* act_host = nullptr);
+double lapply_bytes(const om_csr* A, size_t s, const int32_t* act_host);
+
 
 // trsv.hip
 // act_host (nullable): host copy of the active mask, used for byte accounting

@@ -6,6 +6,9 @@
 // sums are combined with cross-lane shuffles.  Batch items (blockIdx.y) share
 // the column indices and row pointers; each has its own values.  The same
 // kernel applies A^H through the stored conjugate transpose.
+#include <cstdlib>
+#include <cstring>
+
 #include "common.hpp"
 #include "cplx.hpp"
 #include "kernels.hpp"
@@ -59,9 +62,17 @@ double spmv_bytes(const om_csr* A, size_t s, const int32_t* act_host) {
     return na * ((double)A->nnz * (double)(s + 4) + 4.0 * (double)(A->n + 1) + 2.0 * (double)A->n * (double)s);
 }
 
+// OMSS_SPMV=stencil: products with a model matrix (not its adjoint) are
+// evaluated matrix-free (lapply.hip)
+static bool stencil_products() {
+    const char* e = std::getenv("OMSS_SPMV");
+    return e && std::strcmp(e, "stencil") == 0;
+}
+
 template <typename VT>
 om_status spmv(const om_csr* A, int adjoint, const VT* x, VT* y, const int32_t* active, hipStream_t s,
                const int32_t* act_host) {
+    if (!adjoint && A->has_model && stencil_products()) return lapply<VT>(A, x, y, active, s, act_host);
     constexpr int G = 8;
     const int TPB = 256;
     const int32_t* rp = adjoint ? A->t_row_ptr.p : A->row_ptr.p;

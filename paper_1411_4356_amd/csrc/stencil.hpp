@@ -22,14 +22,12 @@ struct Dims {
     int64_t n;
 };
 
-// Candidate `slot` (0..11) of row p: returns false if the column is outside
-// the truncated space; otherwise sets q and the value for parameters P.
-__host__ __device__ inline bool stencil_entry(int slot, int64_t p, const Dims& d, const DevParams& P,
-                                              int64_t& q, double2& v) {
+// Candidate `slot` (0..11) of row p = l*N + k with k = (ik, jk), l = (il, jl)
+// already decoded: returns false if the column is outside the truncated
+// space; otherwise sets q and the value for parameters P.
+__host__ __device__ inline bool stencil_entry_at(int slot, int64_t p, int ik, int jk, int il, int jl, const Dims& d,
+                                                 const DevParams& P, int64_t& q, double2& v) {
     const int64_t N = d.N;
-    const int64_t l = p / N, k = p - l * N;
-    const int ik = (int)(k / d.nm), jk = (int)(k - (int64_t)ik * d.nm);
-    const int il = (int)(l / d.nm), jl = (int)(l - (int64_t)il * d.nm);
     const int nm = d.nm, nc = d.nc;
     switch (slot) {
         case 0:  // bra, cavity down: l' = (il-1, jl); +i E sqrt(il)
@@ -76,5 +74,14 @@ __host__ __device__ inline bool stencil_entry(int slot, int64_t p, const Dims& d
     return false;
 }
 
+// The same for row p, decoded here.
+__host__ __device__ inline bool stencil_entry(int slot, int64_t p, const Dims& d, const DevParams& P,
+                                              int64_t& q, double2& v) {
+    const int64_t N = d.N;
+    const int64_t l = p / N, k = p - l * N;
+    const int ik = (int)(k / d.nm), jk = (int)(k - (int64_t)ik * d.nm);
+    const int il = (int)(l / d.nm), jl = (int)(l - (int64_t)il * d.nm);
+    return stencil_entry_at(slot, p, ik, jk, il, jl, d, P, q, v);
+}
 
 }  // namespace omss

@@ -97,6 +97,62 @@ def test_spmv_matches_oracle(ci, adjoint):
         assert np.all(np.abs(y32[b] - ref) <= 2e-6 * bound)
 
 
+@pytest.mark.parametrize("mode", [model.TRACE_NONE, model.TRACE_REPLACE, model.TRACE_ADD])
+@pytest.mark.parametrize("permuted", [False, True])
+@pytest.mark.parametrize("ci", range(len(CASES)))
+def test_matrix_free_apply_matches_oracle(ci, permuted, mode):
+    """liouvillian_apply re-evaluates every row of the constrained matrix from
+    the model parameters (Eq. (3) in the Fock basis, Eq. (4), the trace row of
+    Eq. (5)) instead of reading stored entries: equal, within the rounding
+    bound of the row sums, to the oracle's Kronecker-built matrix (permuted as
+    rcm_permute permutes it) times x, per batch item and in both precisions."""
+    p = CASES[ci]
+    ps = [p, p.replace(E=p.E * 1.5)]
+    A, _ = P.liouvillian_build(ps, trace_mode=mode)
+    if permuted:
+        B, perm, _ = P.rcm_permute(A)
+    else:
+        B, perm = A, None
+    X = W.random_complex(B.n, seed=12, count=2)
+    y = to_host(P.liouvillian_apply(B, to_dev(X)))
+    y32 = to_host(P.liouvillian_apply(B, to_dev(X, torch.complex64)))
+    for b, q in enumerate(ps):
+        Lt, _, _ = _oracle_system(q, mode)
+        Bo = ordering.permute(Lt, perm) if permuted else Lt
+        ref = Bo @ X[b]
+        bound = abs(Bo) @ np.abs(X[b])
+        assert np.all(np.abs(y[b] - ref) <= 1e-14 * bound + 1e-300)
+        assert np.all(np.abs(y32[b] - ref) <= 2e-6 * bound)
+
+
+def test_solver_with_matrix_free_products(monkeypatch):
+    """With OMSS_SPMV=stencil the solver's products with the system matrix
+    run matrix-free (the kernel class "lapply" records launches) and the
+    steady state is the stored-matrix one and the oracle's."""
+    import ctypes as C
+    lib = P.lib()
+    p = W.TINY
+    opts = dict(drop_tol=W.TINY_OPTS.drop_tol, fill_factor=W.TINY_OPTS.fill_factor, m=W.TINY_OPTS.restart,
+                tol=W.TINY_OPTS.tol)
+    rho0, info0, _ = P.steady_state(p, **opts)
+    monkeypatch.setenv("OMSS_SPMV", "stencil")
+    lib.om_profile_enable(1)
+    lib.om_profile_reset()
+    try:
+        rho1, info1, _ = P.steady_state(p, **opts)
+        torch.cuda.synchronize()
+        launches, ms, nbytes = C.c_int64(), C.c_double(), C.c_double()
+        lib.om_profile_query(b"lapply", C.byref(launches), C.byref(ms), C.byref(nbytes))
+    finally:
+        lib.om_profile_enable(0)
+    assert launches.value > 0
+    assert info1["gmres"]["relres_true"] <= W.TINY_OPTS.tol
+    r0, r1 = rho0[0].cpu().numpy(), rho1[0].cpu().numpy()
+    ro, _ = direct.steady_state(p)
+    assert np.max(np.abs(r1 - r0)) <= 1e-10
+    assert np.max(np.abs(r1 - ro)) <= 1e-9
+
+
 def _factored(p, d, fill, **kw):
     A, _ = P.liouvillian_build(p)
     B, perm, _ = P.rcm_permute(A)
