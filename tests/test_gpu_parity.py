@@ -479,6 +479,28 @@ def test_multi_rhs_solve_with_shared_factor(nb, monkeypatch):
         assert np.max(np.abs(rho[b] - ro)) <= 1e-8
 
 
+def test_full_size_matrix_free_apply_against_oracle():
+    """The matrix-free product and the CSR SpMV at the batch workload's full
+    size (360,000 rows, eight items, RCM order, the launch bench.py times):
+    every row of two items against the oracle's Kronecker-built constrained
+    matrix, permuted as rcm_permute permutes it, within the rounding bound
+    of the row sums."""
+    params = W.batch_params()
+    A, _ = P.liouvillian_build(params)
+    B, perm, _ = P.rcm_permute(A)
+    X = W.random_complex(B.n, seed=21, count=len(params))
+    xd = to_dev(X)
+    y = to_host(P.liouvillian_apply(B, xd))
+    yc = to_host(P.csr_spmv(B, xd))
+    for b in (0, len(params) - 1):
+        Lt, _, _ = model.constrained_system(model.liouvillian(params[b]))
+        Bo = ordering.permute(Lt, perm)
+        ref = Bo @ X[b]
+        bound = abs(Bo) @ np.abs(X[b])
+        assert np.all(np.abs(y[b] - ref) <= 1e-14 * bound + 1e-300)
+        assert np.all(np.abs(yc[b] - ref) <= 1e-14 * bound + 1e-300)
+
+
 def test_full_size_batch_against_oracle_system():
     """The 360,000-row batch workload as bench.py runs it (eight pump
     amplitudes, one ILUT factor of the median-E item, d = 1e-6, p = 400,
