@@ -205,8 +205,13 @@ om_status ilu_factor_impl(const om_csr* Ain, double drop_tol, double fill_factor
         OM_TRY(ilu_apply_dev(M.get(), 0, OM_C128, e.p, e.p, nullptr, s));
         OM_HIP(hipMemcpyAsync(ones.data(), e.p, ones.size() * sizeof(double2), hipMemcpyDeviceToHost, s));
         OM_HIP(hipStreamSynchronize(s));
+        // a non-finite entry (an application that overflows) makes the estimate infinite
         double c = 0;
-        for (const double2& v : ones) c = std::max(c, std::sqrt(v.x * v.x + v.y * v.y));
+        for (const double2& v : ones) {
+            const double a = std::sqrt(v.x * v.x + v.y * v.y);
+            c = std::isfinite(a) ? std::max(c, a) : INFINITY;
+            if (!std::isfinite(c)) break;
+        }
         S.condest = c;
     }
     M->stats = S;

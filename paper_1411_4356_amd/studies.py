@@ -1,0 +1,146 @@
+"""Parameter studies of the paper's results section, run on the device path.
+
+``detuning_sweep``   Fig. 4(a-c): for each detuning and thermal occupation,
+                     the fill factor and condition estimate of the
+                     RCM-ordered ILUT preconditioner (Sec. II, Sec. IV) and
+                     the restarted-GMRES steps to a tolerance, with the
+                     observables of the solution.
+``rcm_reduction``    Fig. 2: bandwidth and profile of the constrained
+                     Liouvillian before and after reverse Cuthill-McKee
+                     (Sec. III) over a grid of truncations, and the
+                     reduction factors B/B_RCM and P/P_RCM.
+
+Every number comes from the library (build, RCM, ILUT, GMRES in libomss.so);
+this module only loops over parameters and collects the results.  The
+direct-LU and COLAMD curves of those figures are comparison systems and are
+not reproduced.
+
+Command line (one JSON record per line on stdout)::
+
+    python -m paper_1411_4356_amd.studies detuning --nc 4 --nm 200 \\
+        --deltas -1,-0.5,0,0.5,1 --nth 0,1e-15,3
+    python -m paper_1411_4356_amd.studies rcm --nc 2,4,6 --nm 10,20,40
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+import time
+from typing import Iterable, List
+
+import torch
+
+from . import api
+from ._lib import OmError
+
+#: Fig. 4(a-d) operator, in units of omega_m: kappa = 0.2, g0 = 2.5 kappa,
+#: Q_m = 1e4, E = 0.1, N_c = 4, N_m = 200 (the detuning and n_th are swept).
+FIG4_BASE = dict(nc=4, nm=200, delta=0.0, omega_m=1.0, g0=0.5, E=0.1, kappa=0.2, gamma_m=1e-4, n_th=3.0)
+#: its preconditioner: drop tolerance d = 1e-4 and fill limit p = 100.
+FIG4_ILU = dict(drop_tol=1e-4, fill_factor=100.0)
+
+
+def _with(base: dict, **kw) -> dict:
+    p = dict(base)
+    p.update(kw)
+    return p
+
+
+def solve_point(params: dict, drop_tol: float, fill_factor: float, m: int = 50, tol: float = 1e-12,
+                maxiter: int = 1000) -> dict:
+    """One parameter point through build -> RCM -> ILUT (with the condition
+    estimate ||(LU)^-1 e||_inf) -> GMRES(m): a record of the preconditioner's
+    fill and condition estimate, the steps, the final residual and the
+    observables, or of the breakdown."""
+    rec = {k: params[k] for k in ("nc", "nm", "delta", "g0", "E", "kappa", "gamma_m", "n_th")}
+    t0 = time.perf_counter()
+    A, w = api.liouvillian_build(params)
+    B, perm, order = api.rcm_permute(A)
+    rec.update(n=B.n, nnz=B.nnz, B0=order["B0"], B1=order["B1"], P0=order["P0"], P1=order["P1"])
+    try:
+        M = api.ilu_factor(B, drop_tol, fill_factor, condest=True)
+    except OmError as e:
+        rec.update(status="ilu_breakdown", error=str(e), seconds=time.perf_counter() - t0)
+        return rec
+    rec.update(fill=M.stats["fill"], condest=M.stats["condest"], repaired_pivots=M.stats["repaired_pivots"])
+    # right-hand side w e_0 of the constrained system, in the RCM ordering
+    iperm0 = int((perm == 0).nonzero()[0][0])
+    b = torch.zeros(B.n, dtype=torch.complex128, device="cuda")
+    b[iperm0] = complex(w[0])
+    try:
+        x, info = api.gmres_solve(B, M, b, m=m, tol=tol, maxiter=maxiter, allow_notconv=True)
+    except OmError as e:
+        # e.g. a preconditioner whose application overflows
+        rec.update(status="gmres_breakdown", error=str(e), converged=False, seconds=time.perf_counter() - t0)
+        return rec
+    torch.cuda.synchronize()
+    rec.update(status=info["status"], iters=info["iters"], relres=info["relres_true"],
+               converged=bool(info["converged"]), seconds=time.perf_counter() - t0)
+    if info["converged"]:
+        n_a, n_b, fano = (float(v) for v in api.observables(B, x)[0])
+        rec.update(n_a=n_a, n_b=n_b, fano=fano)
+    return rec
+
+
+def detuning_sweep(base: dict, deltas: Iterable[float], n_th_values: Iterable[float], drop_tol: float,
+                   fill_factor: float, m: int = 50, tol: float = 1e-12, maxiter: int = 1000) -> List[dict]:
+    """Fig. 4(a-c): one record per (n_th, detuning).  n_th = 0 is solved as
+    given (no substitution), so that it can be set against n_th = 1e-15."""
+    return [solve_point(_with(base, delta=float(d), n_th=float(t)), drop_tol, fill_factor, m, tol, maxiter)
+            for t in n_th_values for d in deltas]
+
+
+def rcm_reduction(base: dict, nc_values: Iterable[int], nm_values: Iterable[int]) -> List[dict]:
+    """Fig. 2: B, P of the constrained Liouvillian in the natural order and
+    after RCM, and the factors B/B_RCM and P/P_RCM, per (N_c, N_m)."""
+    out = []
+    for nc in nc_values:
+        for nm in nm_values:
+            A, _ = api.liouvillian_build(_with(base, nc=int(nc), nm=int(nm)))
+            t0 = time.perf_counter()
+            B, _, o = api.rcm_permute(A)
+            out.append(dict(nc=int(nc), nm=int(nm), n=A.n, nnz=A.nnz, B0=o["B0"], B1=o["B1"], P0=o["P0"],
+                            P1=o["P1"], B_factor=o["B0"] / o["B1"], P_factor=o["P0"] / o["P1"],
+                            rcm_seconds=time.perf_counter() - t0))
+    return out
+
+
+def _floats(s: str) -> List[float]:
+    return [float(v) for v in s.split(",") if v]
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser(prog="python -m paper_1411_4356_amd.studies")
+    sub = ap.add_subparsers(dest="study", required=True)
+    d = sub.add_parser("detuning", help="Fig. 4(a-c) detuning sweep")
+    d.add_argument("--nc", type=int, default=FIG4_BASE["nc"])
+    d.add_argument("--nm", type=int, default=FIG4_BASE["nm"])
+    d.add_argument("--deltas", default="-1,-0.5,0,0.5,1")
+    d.add_argument("--nth", default="0,1e-15,3")
+    d.add_argument("--drop-tol", type=float, default=FIG4_ILU["drop_tol"])
+    d.add_argument("--fill", type=float, default=FIG4_ILU["fill_factor"])
+    d.add_argument("--restart", type=int, default=50)
+    d.add_argument("--tol", type=float, default=1e-12)
+    d.add_argument("--maxiter", type=int, default=1000)
+    r = sub.add_parser("rcm", help="Fig. 2 bandwidth / profile reduction")
+    r.add_argument("--nc", default="2,4,6,8")
+    r.add_argument("--nm", default="10,20,40,80")
+    a = ap.parse_args(argv)
+    if not torch.cuda.is_available():
+        print("the studies run on a HIP device", file=sys.stderr)
+        return 2
+    if a.study == "detuning":
+        base = _with(FIG4_BASE, nc=a.nc, nm=a.nm)
+        for t in _floats(a.nth):
+            for dl in _floats(a.deltas):
+                rec = solve_point(_with(base, delta=dl, n_th=t), a.drop_tol, a.fill, a.restart, a.tol, a.maxiter)
+                print(json.dumps(rec), flush=True)
+    else:
+        for rec in rcm_reduction(FIG4_BASE, [int(v) for v in _floats(a.nc)], [int(v) for v in _floats(a.nm)]):
+            print(json.dumps(rec), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
