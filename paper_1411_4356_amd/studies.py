@@ -5,6 +5,10 @@
                      RCM-ordered ILUT preconditioner (Sec. II, Sec. IV) and
                      the restarted-GMRES steps to a tolerance, with the
                      observables of the solution.
+``phonon_distribution``  Fig. 5(b): the mechanical phonon-number
+                     distribution and Fano factor of one steady state
+                     (Sec. IV; the Wigner function and the limit-cycle fits
+                     are not computed).
 ``rcm_reduction``    Fig. 2: bandwidth and profile of the constrained
                      Liouvillian before and after reverse Cuthill-McKee
                      (Sec. III) over a grid of truncations, and the
@@ -20,6 +24,7 @@ Command line (one JSON record per line on stdout)::
     python -m paper_1411_4356_amd.studies detuning --nc 4 --nm 200 \\
         --deltas -1,-0.5,0,0.5,1 --nth 0,1e-15,3
     python -m paper_1411_4356_amd.studies rcm --nc 2,4,6 --nm 10,20,40
+    python -m paper_1411_4356_amd.studies fig5
 """
 from __future__ import annotations
 
@@ -39,6 +44,11 @@ from ._lib import OmError
 FIG4_BASE = dict(nc=4, nm=200, delta=0.0, omega_m=1.0, g0=0.5, E=0.1, kappa=0.2, gamma_m=1e-4, n_th=3.0)
 #: its preconditioner: drop tolerance d = 1e-4 and fill limit p = 100.
 FIG4_ILU = dict(drop_tol=1e-4, fill_factor=100.0)
+#: Fig. 5 operator: E = 0.45, kappa = 0.05, Delta = -2 kappa, g0 = 0.32,
+#: n_th = 20, N_c = 5, N_m = 160 (Q_m = 1e4 as in Fig. 4), with d = 1e-4 and
+#: p = 200.
+FIG5_BASE = dict(nc=5, nm=160, delta=-0.1, omega_m=1.0, g0=0.32, E=0.45, kappa=0.05, gamma_m=1e-4, n_th=20.0)
+FIG5_ILU = dict(drop_tol=1e-4, fill_factor=200.0)
 
 
 def _with(base: dict, **kw) -> dict:
@@ -91,6 +101,23 @@ def detuning_sweep(base: dict, deltas: Iterable[float], n_th_values: Iterable[fl
             for t in n_th_values for d in deltas]
 
 
+def phonon_distribution(params: dict, drop_tol: float, fill_factor: float, m: int = 50, tol: float = 1e-12,
+                        maxiter: int = 1000) -> dict:
+    """Fig. 5(b): P(n) = sum_i rho[(i, n), (i, n)] of the steady state (the
+    mechanical marginal of the diagonal), with <b^dag b> and the Fano factor
+    <(Delta N_b)^2> / <N_b> of the solver, and the solve's statistics."""
+    t0 = time.perf_counter()
+    rho, info, res = api.steady_state(params, drop_tol=drop_tol, fill_factor=fill_factor, m=m, tol=tol,
+                                      maxiter=maxiter)
+    nc, nm = int(params["nc"]), int(params["nm"])
+    diag = torch.diagonal(rho[0]).real.reshape(nc, nm).sum(dim=0)
+    torch.cuda.synchronize()
+    return dict(nc=nc, nm=nm, n=nc * nc * nm * nm, n_b=float(res["n_b"][0]), n_a=float(res["n_a"][0]),
+                fano=float(res["fano"][0]), relres=float(res["relres"][0]), iters=info["gmres"]["iters"],
+                fill=info["ilu"]["fill"], seconds=time.perf_counter() - t0,
+                distribution=[float(v) for v in diag.cpu()])
+
+
 def rcm_reduction(base: dict, nc_values: Iterable[int], nm_values: Iterable[int]) -> List[dict]:
     """Fig. 2: B, P of the constrained Liouvillian in the natural order and
     after RCM, and the factors B/B_RCM and P/P_RCM, per (N_c, N_m)."""
@@ -123,6 +150,12 @@ def main(argv=None) -> int:
     d.add_argument("--restart", type=int, default=50)
     d.add_argument("--tol", type=float, default=1e-12)
     d.add_argument("--maxiter", type=int, default=1000)
+    f = sub.add_parser("fig5", help="Fig. 5(b) phonon distribution and Fano factor")
+    f.add_argument("--nc", type=int, default=FIG5_BASE["nc"])
+    f.add_argument("--nm", type=int, default=FIG5_BASE["nm"])
+    f.add_argument("--drop-tol", type=float, default=FIG5_ILU["drop_tol"])
+    f.add_argument("--fill", type=float, default=FIG5_ILU["fill_factor"])
+    f.add_argument("--tol", type=float, default=1e-12)
     r = sub.add_parser("rcm", help="Fig. 2 bandwidth / profile reduction")
     r.add_argument("--nc", default="2,4,6,8")
     r.add_argument("--nm", default="10,20,40,80")
@@ -136,6 +169,12 @@ def main(argv=None) -> int:
             for dl in _floats(a.deltas):
                 rec = solve_point(_with(base, delta=dl, n_th=t), a.drop_tol, a.fill, a.restart, a.tol, a.maxiter)
                 print(json.dumps(rec), flush=True)
+    elif a.study == "fig5":
+        try:
+            rec = phonon_distribution(_with(FIG5_BASE, nc=a.nc, nm=a.nm), a.drop_tol, a.fill, tol=a.tol)
+        except OmError as e:
+            rec = dict(nc=a.nc, nm=a.nm, drop_tol=a.drop_tol, fill_factor=a.fill, status="breakdown", error=str(e))
+        print(json.dumps(rec), flush=True)
     else:
         for rec in rcm_reduction(FIG4_BASE, [int(v) for v in _floats(a.nc)], [int(v) for v in _floats(a.nm)]):
             print(json.dumps(rec), flush=True)

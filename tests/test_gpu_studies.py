@@ -63,3 +63,17 @@ def test_rcm_reduction_matches_oracle():
         s1 = ordering.bandwidth_profile(ordering.permute(Lt, ordering.rcm(Lt)))
         assert (r["B0"], r["P0"], r["B1"], r["P1"]) == (s0["B"], s0["P"], s1["B"], s1["P"])
         assert r["B_factor"] > 1.0
+
+
+def test_phonon_distribution_matches_oracle():
+    """Fig. 5(b) quantities on a small truncation of the Fig. 5 operator: the
+    mechanical phonon distribution (diagonal of the mechanical marginal) and
+    the Fano factor equal the oracle's direct solve."""
+    params = dict(studies.FIG5_BASE, nc=3, nm=14)
+    r = studies.phonon_distribution(params, drop_tol=1e-6, fill_factor=60.0)
+    rho, ob = direct.steady_state(_model(params))
+    pn = np.real(np.diag(rho)).reshape(params["nc"], params["nm"]).sum(axis=0)
+    assert r["relres"] <= 1e-12
+    assert np.max(np.abs(np.array(r["distribution"]) - pn)) <= 1e-9
+    assert abs(sum(r["distribution"]) - 1.0) <= 1e-12
+    assert abs(r["fano"] - ob["fano"]) <= 1e-8 * abs(ob["fano"])
