@@ -64,6 +64,9 @@ typedef struct {
     double kappa;       /* cavity damping rate, >= 0 */
     double gamma_m;     /* mechanical damping rate Gamma_m, >= 0 */
     double n_th;        /* thermal occupation of the mechanical bath, >= 0 */
+    double g2;          /* quadratic coupling g2 (b + b^dag)^2 a^dag a added to the
+                           Hamiltonian of Eq. (1) (the "membrane in the middle"
+                           variant of Sec. V); 0 for Eq. (1) itself */
 } om_params;
 
 typedef struct om_csr om_csr;   /* device CSR: one pattern, `batch` value sets */

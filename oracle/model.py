@@ -49,12 +49,18 @@ def _dag(op: sp.spmatrix) -> sp.csr_matrix:
 
 def hamiltonian(p) -> sp.csr_matrix:
     """Eq. (1): H = -Delta a^dag a + omega_m b^dag b + g0 (b + b^dag) a^dag a
-    + E (a + a^dag), hbar = 1."""
+    + E (a + a^dag), hbar = 1; plus g2 (b + b^dag)^2 a^dag a when p has a
+    nonzero g2 (the quadratic coupling the conclusion (Sec. V) names as a
+    variant), with the truncated operators multiplied as matrices."""
     a, b = mode_operators(p.nc, p.nm)
     ad, bd = _dag(a), _dag(b)
     na = ad @ a
     nb = bd @ b
     H = (-p.delta) * na + p.omega_m * nb + p.g0 * ((b + bd) @ na) + p.E * (a + ad)
+    g2 = getattr(p, "g2", 0.0)
+    if g2:
+        x = b + bd
+        H = H + g2 * ((x @ x) @ na)
     return H.tocsr()
 
 

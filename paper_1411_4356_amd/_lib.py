@@ -20,7 +20,7 @@ OM_ILU_C64, OM_ILU_ADJOINT, OM_ILU_CONDEST, OM_ILU_KEEP_HOST, OM_ILU_SHARED = 1,
 class om_params(C.Structure):
     _fields_ = [("nc", C.c_int32), ("nm", C.c_int32), ("delta", C.c_double), ("omega_m", C.c_double),
                 ("g0", C.c_double), ("E", C.c_double), ("kappa", C.c_double), ("gamma_m", C.c_double),
-                ("n_th", C.c_double)]
+                ("n_th", C.c_double), ("g2", C.c_double)]
 
 
 class om_order_stats(C.Structure):

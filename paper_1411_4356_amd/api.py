@@ -29,10 +29,10 @@ def _params_array(params) -> tuple:
         params = [params]
     arr = (L.om_params * len(params))()
     for i, p in enumerate(params):
-        g = (lambda k, d=None: p[k] if isinstance(p, dict) else getattr(p, k, d))
+        g = (lambda k, d=None: p.get(k, d) if isinstance(p, dict) else getattr(p, k, d))
         arr[i] = L.om_params(int(g("nc")), int(g("nm")), float(g("delta")), float(g("omega_m", 1.0) or 1.0),
                              float(g("g0")), float(g("E")), float(g("kappa")), float(g("gamma_m")),
-                             float(g("n_th")))
+                             float(g("n_th")), float(g("g2", 0.0) or 0.0))
     return arr, len(params)
 
 

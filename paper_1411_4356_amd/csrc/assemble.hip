@@ -3,20 +3,24 @@
 //
 // Row p = l*N + k holds the equation for rho[k, l]; k = ik*nm + jk and
 // l = il*nm + jl (a = a_c (x) I, b = I (x) b_m, Sec. III).  Each row has at
-// most twelve entries, evaluated in closed form from Eq. (1) and Eq. (3):
+// most sixteen entries, evaluated in closed form from Eq. (1) and Eq. (3):
 //   diagonal        -i (h_k - h_l) - (c_k + c_l) / 2,
-//                   h = -Delta i + omega_m j,
+//                   h = -Delta i + omega_m j + g2 i D2(j),
+//                   D2(j) = j + (j + 1) [j < nm - 1],
 //                   c = kappa i + Gamma (1 + n_th) j + Gamma n_th (j + 1) [j < nm - 1]
 //   ket side  -i H[k, k'] rho[k', l]  (k' a neighbour of k in H)
 //   bra side  +i rho[k, l'] H[l', l]
 //   jumps     kappa a rho a^dag, Gamma (1 + n_th) b rho b^dag, Gamma n_th b^dag rho b
-// with H[(i,j),(i+-1,j)] = E sqrt(max i) and H[(i,j),(i,j+-1)] = g0 i sqrt(max j).
-// The twelve candidate columns are, in increasing order,
-//   p - nm N, p - N - 1, p - N, p - nm, p - 1, p, p + 1, p + nm, p + N,
-//   p + N + 1, p + nm N, p + nm (N + 1)
-// (distinct and increasing for nc, nm >= 2).  An entry is stored when its value
-// is nonzero for at least one item of the batch.  Row 0 is rebuilt on the host
-// for the trace condition.
+// with H[(i,j),(i+-1,j)] = E sqrt(max i), H[(i,j),(i,j+-1)] = g0 i sqrt(max j)
+// and, for the quadratic coupling g2 (b + b^dag)^2 a^dag a (Sec. V; zero in
+// Eq. (1)), H[(i,j),(i,j+-2)] = g2 i sqrt(m + 1) sqrt(m + 2), m = min(j, j').
+// The sixteen candidate columns are, in increasing order,
+//   p - nm N, p - 2N, p - N - 1, p - N, p - nm, p - 2, p - 1, p, p + 1, p + 2,
+//   p + nm, p + N, p + N + 1, p + 2N, p + nm N, p + nm (N + 1)
+// (distinct and increasing for nc >= 2, nm >= 3; with nm = 2 the +-2 columns
+// never exist).  An entry is stored when its value is nonzero for at least one
+// item of the batch (so g2 = 0 stores none of the quadratic entries).  Row 0
+// is rebuilt on the host for the trace condition.
 #include <hipcub/hipcub.hpp>
 
 #include <algorithm>
@@ -35,7 +39,7 @@ __global__ void count_kernel(Dims d, const DevParams* P, int batch, int64_t firs
     const int64_t p = first_row + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= d.n) return;
     int c = 0;
-    for (int s = 0; s < 12; ++s) {
+    for (int s = 0; s < NSLOT; ++s) {
         int64_t q; double2 v;
         if (!stencil_entry(s, p, d, P[0], q, v)) continue;
         bool nz = nonzero(v);
@@ -53,7 +57,7 @@ __global__ void fill_kernel(Dims d, const DevParams* P, int batch, int64_t first
     const int64_t p = first_row + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= d.n) return;
     int64_t pos = row_ptr[p];
-    for (int s = 0; s < 12; ++s) {
+    for (int s = 0; s < NSLOT; ++s) {
         int64_t q; double2 v;
         if (!stencil_entry(s, p, d, P[0], q, v)) continue;
         bool nz = nonzero(v);
@@ -90,7 +94,7 @@ __global__ void to_c64_kernel(const double2* in, float2* out, int64_t count) {
 }
 
 static bool finite_params(const om_params& p) {
-    const double v[] = {p.delta, p.omega_m, p.g0, p.E, p.kappa, p.gamma_m, p.n_th};
+    const double v[] = {p.delta, p.omega_m, p.g0, p.E, p.kappa, p.gamma_m, p.n_th, p.g2};
     for (double x : v)
         if (!std::isfinite(x)) return false;
     return true;
@@ -122,7 +126,7 @@ om_status validate_params(const om_params* params, int32_t batch) {
 }
 
 static DevParams dev_params(const om_params& p) {
-    return DevParams{p.delta, p.omega_m, p.g0, p.E, p.kappa, p.gamma_m, p.n_th};
+    return DevParams{p.delta, p.omega_m, p.g0, p.E, p.kappa, p.gamma_m, p.n_th, p.g2};
 }
 
 om_status assemble(const om_params* params, int32_t batch, int32_t trace_mode, uint32_t flags, om_csr* A,
@@ -141,7 +145,7 @@ om_status assemble(const om_params* params, int32_t batch, int32_t trace_mode, u
     // row 0 on the host: the model row, then the trace condition
     std::vector<int64_t> r0col;
     std::vector<std::vector<double2>> r0val(batch);
-    for (int sl = 0; sl < 12; ++sl) {
+    for (int sl = 0; sl < NSLOT; ++sl) {
         int64_t q; double2 v;
         if (!stencil_entry(sl, 0, d, hp[0], q, v)) continue;
         bool nz = v.x != 0.0 || v.y != 0.0;

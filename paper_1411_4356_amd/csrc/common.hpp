@@ -108,7 +108,7 @@ struct om_csr {
     bool permuted = false;
     std::vector<int32_t> perm;
     omss::DevBuf<int32_t> perm_d, iperm_d;
-    // model parameters (7 doubles per item, in the stencil's order) and trace
+    // model parameters (8 doubles per item, in the stencil's order) and trace
     // weights on the device, uploaded by the first matrix-free product
     omss::DevBuf<double> lapply_params, lapply_w;
 };

@@ -3,7 +3,7 @@
 // y = A x where A is the matrix liouvillian_build assembles (Eq. (3) in the
 // Fock basis with column-stacked rho, Eq. (4); row 0 carrying the trace
 // condition of Eq. (5)), possibly symmetrically permuted, without reading
-// any stored entry: every row evaluates its at most 12 stencil entries from
+// any stored entry: every row evaluates its at most 16 stencil entries from
 // the model parameters and gathers the matching unknowns.  Only x and y (and
 // the permutation, if any) cross HBM -- 2s bytes per row instead of the
 // 20 bytes per stored entry plus 2s per row of the CSR product (s = bytes of
@@ -23,10 +23,10 @@ constexpr int LT = 256;
 
 // Rows of A other than the trace row.  Row i of A is model row perm[i]; the
 // unknown of model column q is x[iperm[q]].  The row is decoded once (32-bit:
-// n < 2^31), its twelve candidate entries are evaluated into registers, and
+// n < 2^31), its candidate entries are evaluated into registers, and
 // the index and value gathers of all of them are issued before any is used
 // (a slot outside the truncated space gathers the row's own unknown and adds
-// nothing), so a row waits for two rounds of loads rather than twenty-four.
+// nothing), so a row waits for two rounds of loads rather than one per entry.
 template <typename VT, bool PERM>
 __global__ __launch_bounds__(LT) void lapply_kernel(Dims d, const DevParams* __restrict__ P,
                                                     const int32_t* __restrict__ perm,
@@ -46,23 +46,23 @@ __global__ __launch_bounds__(LT) void lapply_kernel(Dims d, const DevParams* __r
     const int il = (int)(l / nm), jl = (int)(l - (uint32_t)il * nm);
     const DevParams Pb = P[b];
     const VT* xb = x + (int64_t)b * d.n;
-    bool ok[12];
-    int64_t q[12];
-    double2 v[12];
+    bool ok[NSLOT];
+    int64_t q[NSLOT];
+    double2 v[NSLOT];
 #pragma unroll
-    for (int sl = 0; sl < 12; ++sl) {
+    for (int sl = 0; sl < NSLOT; ++sl) {
         ok[sl] = stencil_entry_at(sl, (int64_t)p, ik, jk, il, jl, d, Pb, q[sl], v[sl]);
         if (!ok[sl]) q[sl] = p;
     }
-    int64_t j[12];
+    int64_t j[NSLOT];
 #pragma unroll
-    for (int sl = 0; sl < 12; ++sl) j[sl] = PERM ? (int64_t)iperm[q[sl]] : q[sl];
-    VT xv[12];
+    for (int sl = 0; sl < NSLOT; ++sl) j[sl] = PERM ? (int64_t)iperm[q[sl]] : q[sl];
+    VT xv[NSLOT];
 #pragma unroll
-    for (int sl = 0; sl < 12; ++sl) xv[sl] = xb[j[sl]];
+    for (int sl = 0; sl < NSLOT; ++sl) xv[sl] = xb[j[sl]];
     ST ar = 0, ai = 0;
 #pragma unroll
-    for (int sl = 0; sl < 12; ++sl) {
+    for (int sl = 0; sl < NSLOT; ++sl) {
         if (!ok[sl]) continue;
         const ST vr = (ST)v[sl].x, vi = (ST)v[sl].y;
         ar += vr * xv[sl].x - vi * xv[sl].y;
@@ -114,7 +114,7 @@ __global__ __launch_bounds__(LT) void lapply_trace_kernel(Dims d, const DevParam
     ST ar = wb * tr, ai = wb * ti;
     if (add_model_row) {
         const DevParams Pb = P[b];
-        for (int sl = 0; sl < 12; ++sl) {
+        for (int sl = 0; sl < NSLOT; ++sl) {
             int64_t q;
             double2 v;
             if (!stencil_entry(sl, 0, d, Pb, q, v)) continue;
@@ -150,12 +150,12 @@ om_status lapply(const om_csr* A, const VT* x, VT* y, const int32_t* active, hip
     const Dims d{p0.nc, p0.nm, p0.nc * p0.nm, A->n};
     om_csr* Am = const_cast<om_csr*>(A);
     // per-item parameters and weights, uploaded once per handle
-    static_assert(sizeof(DevParams) == 7 * sizeof(double), "parameter record");
+    static_assert(sizeof(DevParams) == 8 * sizeof(double), "parameter record");
     if (!Am->lapply_params.p) {
         std::vector<double> hp;
         for (int b = 0; b < A->batch; ++b) {
             const om_params& q = A->params[b];
-            for (double v : {q.delta, q.omega_m, q.g0, q.E, q.kappa, q.gamma_m, q.n_th}) hp.push_back(v);
+            for (double v : {q.delta, q.omega_m, q.g0, q.E, q.kappa, q.gamma_m, q.n_th, q.g2}) hp.push_back(v);
         }
         OM_TRY(Am->lapply_params.upload(hp.data(), hp.size(), s));
         OM_TRY(Am->lapply_w.upload(A->w.data(), A->w.size(), s));

@@ -144,7 +144,7 @@ __global__ __launch_bounds__(PT) void grad_kernel(Dims d, const DevParams* __res
     if (p >= 1 && p < n) {
         double2 dv[5];
         for (int t = 0; t < 5; ++t) dv[t] = make_double2(0.0, 0.0);
-        for (int s = 0; s < 12; ++s) {
+        for (int s = 0; s < NSLOT; ++s) {
             int64_t q;
             double2 v;
             if (!stencil_entry(s, p, d, unit[b * 5 + 0], q, v)) continue;

@@ -25,8 +25,10 @@ def _gpu(request):
     announce(request.node.nodeid)
 
 
-# n = 441, 1296 (ragged: not a multiple of 64), 1600, and n_th = 0
-CASES = [W.TINY.replace(nc=3, nm=7), W.TINY.replace(nc=4, nm=9), W.TINY, W.ADJOINT.replace(nc=3, nm=8)]
+# n = 441, 1296 (ragged: not a multiple of 64), 1600, n_th = 0, and the
+# quadratic coupling g2 (b + b^dag)^2 a^dag a of the Sec. V variant
+CASES = [W.TINY.replace(nc=3, nm=7), W.TINY.replace(nc=4, nm=9), W.TINY, W.ADJOINT.replace(nc=3, nm=8),
+         W.TINY.replace(nc=3, nm=8, g2=0.07)]
 
 
 def _oracle_system(p, mode=model.TRACE_REPLACE):

@@ -25,6 +25,31 @@ def test_nnz_matches_counting_formula(nc, nm, n_th):
     assert model.liouvillian(p).nnz == nnz_closed_form(nc, nm, n_th)
 
 
+@pytest.mark.parametrize("nc,nm,n_th", [(2, 3, 0.5), (3, 5, 0.0), (4, 6, 3.0)])
+def test_quadratic_coupling_nnz(nc, nm, n_th):
+    """With the quadratic coupling g2 (b + b^dag)^2 a^dag a (Sec. V), every
+    cavity level i >= 1 couples mechanical levels two apart, on the ket and
+    on the bra side: 2 (nc - 1) 2 (nm - 2) new entries per column block of N,
+    4 N (nc - 1)(nm - 2) in all; its diagonal part adds no entry."""
+    p = W.TINY.replace(nc=nc, nm=nm, n_th=n_th, g2=0.3)
+    N = nc * nm
+    assert model.liouvillian(p).nnz == nnz_closed_form(nc, nm, n_th) + 4 * N * (nc - 1) * (nm - 2)
+
+
+def test_quadratic_coupling_term():
+    """H(g2) - H(0) = g2 (a^dag a) (x) (b + b^dag)^2, with the mechanical
+    position operator written out densely from its matrix elements
+    x[j, j+1] = x[j+1, j] = sqrt(j + 1) and squared in the truncated space."""
+    p = W.TINY.replace(nc=3, nm=6)
+    g2 = 0.37
+    dH = (model.hamiltonian(p.replace(g2=g2)) - model.hamiltonian(p)).toarray() / g2
+    x = np.zeros((p.nm, p.nm))
+    for j in range(p.nm - 1):
+        x[j, j + 1] = x[j + 1, j] = np.sqrt(j + 1.0)
+    expect = np.kron(np.diag(np.arange(p.nc, dtype=float)), x @ x)
+    assert np.max(np.abs(dH - expect)) <= 1e-13
+
+
 def test_fig1_nnz_and_upper_bandwidth():
     g = read_golden("fig1_structure.txt")
     p = W.FIG1
@@ -37,20 +62,22 @@ def test_fig1_nnz_and_upper_bandwidth():
     assert st["B"] > (p.nc * p.nm) ** 2 - 1
 
 
+@pytest.mark.parametrize("g2", [0.0, 0.2])
 @pytest.mark.parametrize("n_th", [0.0, 0.5])
-def test_trace_preservation(n_th):
+def test_trace_preservation(n_th, g2):
     """t^T L = 0: the Lindblad generator preserves the trace (Eq. (3))."""
-    p = W.TINY.replace(nc=3, nm=5, n_th=n_th)
+    p = W.TINY.replace(nc=3, nm=5, n_th=n_th, g2=g2)
     L = model.liouvillian(p)
     t = model.trace_vector(p.nc * p.nm)
     row = L.T @ t
     assert np.max(np.abs(row)) <= 1e-14 * abs(L).max()
 
 
-def test_hermiticity_preservation():
+@pytest.mark.parametrize("g2", [0.0, 0.2])
+def test_hermiticity_preservation(g2):
     """L[rho]^dag = L[rho^dag]: entry (p, q) equals conj of entry
     (sigma p, sigma q), where sigma swaps the ket and bra indices."""
-    p = W.TINY.replace(nc=3, nm=4)
+    p = W.TINY.replace(nc=3, nm=4, g2=g2)
     N = p.nc * p.nm
     D = model.liouvillian(p).toarray()
     idx = np.arange(N * N)

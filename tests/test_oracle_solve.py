@@ -32,12 +32,15 @@ def test_coherent_cavity_at_zero_coupling():
     assert np.max(np.abs(rho - np.kron(rho_c, rho_m))) <= 1e-12
 
 
+@pytest.mark.parametrize("g2", [0.0, 0.25])
 @pytest.mark.parametrize("n_th", [0.5, 2.0])
-def test_thermal_mechanics_without_drive(n_th):
+def test_thermal_mechanics_without_drive(n_th, g2):
     """E = 0: cavity in vacuum, mechanics in the truncated thermal state
     p_n proportional to r^n with r = n_th / (n_th + 1) (detailed balance of the
-    b and b^dag jumps, exact in the truncated space)."""
-    p = W.TINY.replace(nc=3, nm=9, E=0.0, n_th=n_th)
+    b and b^dag jumps, exact in the truncated space).  Both couplings act
+    through a^dag a, which vanishes on the vacuum, so a quadratic coupling g2
+    leaves this state unchanged."""
+    p = W.TINY.replace(nc=3, nm=9, E=0.0, n_th=n_th, g2=g2)
     rho, obs = direct.steady_state(p)
     r = n_th / (n_th + 1.0)
     pn = r ** np.arange(p.nm)

@@ -33,6 +33,7 @@ class ModelParams:
     kappa    -- cavity damping rate.
     gamma_m  -- mechanical damping rate Gamma_m = omega_m / Q_m.
     n_th     -- thermal occupation of the mechanical bath.
+    g2       -- quadratic coupling g2 (b + b^dag)^2 a^dag a (Sec. V variant; 0 in Eq. (1)).
     """
 
     nc: int
@@ -44,6 +45,7 @@ class ModelParams:
     gamma_m: float
     n_th: float
     omega_m: float = 1.0
+    g2: float = 0.0
 
     @property
     def hilbert_dim(self) -> int:
