@@ -21,13 +21,18 @@ namespace {
 
 constexpr int LT = 256;
 
+// the slots of the quadratic coupling g2 (b + b^dag)^2 a^dag a (stencil.hpp)
+__host__ __device__ constexpr bool is_quadratic_slot(int sl) { return sl == 1 || sl == 5 || sl == 9 || sl == 13; }
+
 // Rows of A other than the trace row.  Row i of A is model row perm[i]; the
 // unknown of model column q is x[iperm[q]].  The row is decoded once (32-bit:
 // n < 2^31), its candidate entries are evaluated into registers, and
 // the index and value gathers of all of them are issued before any is used
 // (a slot outside the truncated space gathers the row's own unknown and adds
 // nothing), so a row waits for two rounds of loads rather than one per entry.
-template <typename VT, bool PERM>
+// QUAD = false: no item has a quadratic coupling, and its four slots (whose
+// values would all be zero) are left out at compile time.
+template <typename VT, bool PERM, bool QUAD>
 __global__ __launch_bounds__(LT) void lapply_kernel(Dims d, const DevParams* __restrict__ P,
                                                     const int32_t* __restrict__ perm,
                                                     const int32_t* __restrict__ iperm, const VT* __restrict__ x,
@@ -51,15 +56,17 @@ __global__ __launch_bounds__(LT) void lapply_kernel(Dims d, const DevParams* __r
     double2 v[NSLOT];
 #pragma unroll
     for (int sl = 0; sl < NSLOT; ++sl) {
-        ok[sl] = stencil_entry_at(sl, (int64_t)p, ik, jk, il, jl, d, Pb, q[sl], v[sl]);
+        ok[sl] = (QUAD || !is_quadratic_slot(sl)) && stencil_entry_at(sl, (int64_t)p, ik, jk, il, jl, d, Pb, q[sl], v[sl]);
         if (!ok[sl]) q[sl] = p;
     }
     int64_t j[NSLOT];
 #pragma unroll
-    for (int sl = 0; sl < NSLOT; ++sl) j[sl] = PERM ? (int64_t)iperm[q[sl]] : q[sl];
+    for (int sl = 0; sl < NSLOT; ++sl)
+        if (QUAD || !is_quadratic_slot(sl)) j[sl] = PERM ? (int64_t)iperm[q[sl]] : q[sl];
     VT xv[NSLOT];
 #pragma unroll
-    for (int sl = 0; sl < NSLOT; ++sl) xv[sl] = xb[j[sl]];
+    for (int sl = 0; sl < NSLOT; ++sl)
+        if (QUAD || !is_quadratic_slot(sl)) xv[sl] = xb[j[sl]];
     ST ar = 0, ai = 0;
 #pragma unroll
     for (int sl = 0; sl < NSLOT; ++sl) {
@@ -165,14 +172,19 @@ om_status lapply(const om_csr* A, const VT* x, VT* y, const int32_t* active, hip
     const int32_t* iperm = A->permuted ? A->iperm_d.p : nullptr;
     const bool trace = A->trace_mode != OM_TRACE_NONE;
     ProfScope prof("lapply", s, profile_enabled() ? lapply_bytes(A, sizeof(VT), act_host) : 0.0);
-    if (perm)
-        hipLaunchKernelGGL((lapply_kernel<VT, true>), dim3(blocks_for(A->n, LT), A->batch), dim3(LT), 0, s, d,
-                           reinterpret_cast<const DevParams*>(Am->lapply_params.p), perm, iperm, x, y, active,
-                           trace ? 1 : 0);
+    bool quad = false;
+    for (const om_params& q : A->params) quad = quad || q.g2 != 0.0;
+    const dim3 grid(blocks_for(A->n, LT), A->batch);
+    const DevParams* dp = reinterpret_cast<const DevParams*>(Am->lapply_params.p);
+    const int skip0 = trace ? 1 : 0;
+    if (perm && quad)
+        hipLaunchKernelGGL((lapply_kernel<VT, true, true>), grid, dim3(LT), 0, s, d, dp, perm, iperm, x, y, active, skip0);
+    else if (perm)
+        hipLaunchKernelGGL((lapply_kernel<VT, true, false>), grid, dim3(LT), 0, s, d, dp, perm, iperm, x, y, active, skip0);
+    else if (quad)
+        hipLaunchKernelGGL((lapply_kernel<VT, false, true>), grid, dim3(LT), 0, s, d, dp, perm, iperm, x, y, active, skip0);
     else
-        hipLaunchKernelGGL((lapply_kernel<VT, false>), dim3(blocks_for(A->n, LT), A->batch), dim3(LT), 0, s, d,
-                           reinterpret_cast<const DevParams*>(Am->lapply_params.p), perm, iperm, x, y, active,
-                           trace ? 1 : 0);
+        hipLaunchKernelGGL((lapply_kernel<VT, false, false>), grid, dim3(LT), 0, s, d, dp, perm, iperm, x, y, active, skip0);
     OM_HIP(hipGetLastError());
     if (trace) {
         hipLaunchKernelGGL((lapply_trace_kernel<VT>), dim3(A->batch), dim3(LT), 0, s, d,
