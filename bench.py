@@ -147,7 +147,9 @@ def cpu_baseline(params, opts, budget_s):
     # thread pool
     from oracle import direct as _direct
     threads = 1
+    how = "Kronecker build + scipy sparse LU (COLAMD, SuperLU)"
     if params[0].n <= _direct.DENSE_LIMIT:
+        how = "Kronecker build + dense LU (LAPACK)"
         threads = os.cpu_count() or 1
         try:
             from threadpoolctl import threadpool_info
@@ -177,11 +179,11 @@ def cpu_baseline(params, opts, budget_s):
     if done == 0:
         return {"value": 1.0 / budget_s, "unit": "solves/s", "cores": int(threads), "kind": "oracle",
                 "bound": "upper",
-                "sample": f"batch item 0 (n={params[0].n}): Kronecker build + scipy sparse LU (COLAMD) did not finish "
+                "sample": f"batch item 0 (n={params[0].n}): {how} did not finish "
                           f"within {budget_s:.0f} s; value is the upper bound 1/{budget_s:.0f} s"}
     return {"value": done / dt, "unit": "solves/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{done} of {len(params)} batch items: Kronecker build + scipy sparse LU (COLAMD) of the "
-                      f"constrained system, {dt:.1f} s wall"}
+            "sample": f"{done} of {len(params)} batch items (n={params[0].n}): {how} of the constrained system, "
+                      f"{dt:.1f} s wall"}
 
 
 def main():
