@@ -142,20 +142,18 @@ def cpu_baseline(params, opts, budget_s):
     the budget the reported value is an upper bound (1 / budget)."""
     import multiprocessing as mp
 
-    # the oracle's sparse LU (SuperLU through scipy) and its Kronecker build
-    # run on one thread; only its dense path (small systems) uses the BLAS
-    # thread pool
+    # both oracle paths (dense LAPACK for small systems, SuperLU's supernodal
+    # LU otherwise) run their dense kernels on the BLAS thread pool
     from oracle import direct as _direct
-    threads = 1
     how = "Kronecker build + scipy sparse LU (COLAMD, SuperLU)"
     if params[0].n <= _direct.DENSE_LIMIT:
         how = "Kronecker build + dense LU (LAPACK)"
-        threads = os.cpu_count() or 1
-        try:
-            from threadpoolctl import threadpool_info
-            threads = max([t.get("num_threads", 1) for t in threadpool_info()] or [1])
-        except Exception:
-            pass
+    threads = os.cpu_count() or 1
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([t.get("num_threads", 1) for t in threadpool_info()] or [1])
+    except Exception:
+        pass
     ctx = mp.get_context("spawn")
     t0 = time.perf_counter()
     done = 0

@@ -25,4 +25,4 @@ def test_cpu_baseline_times_the_oracle():
     assert "n=1600" in out["sample"] and out["cores"] >= 1
     # a sample that cannot finish is reported as an upper bound
     big = bench.cpu_baseline(W.batch_params()[:1], None, 1.0)
-    assert big["bound"] == "upper" and abs(big["value"] - 1.0) < 1e-12 and big["cores"] == 1
+    assert big["bound"] == "upper" and abs(big["value"] - 1.0) < 1e-12 and big["cores"] >= 1
