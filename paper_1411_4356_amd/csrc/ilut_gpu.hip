@@ -49,6 +49,7 @@ constexpr int WBITS_MAX = 1 << 16;  // largest band window (lb + ub + 1)
 constexpr int RADIX_BITS = 11;
 constexpr int FLAG_STRIDE = 32;
 constexpr int UF = 4;               // U-row entries per thread in flight in an update
+constexpr int WB = 16;              // window positions per thread in flight in the unstaged dropping
 constexpr int RADIX = 1 << RADIX_BITS;
 
 struct IlutDevArgs {
@@ -187,14 +188,21 @@ __device__ unsigned long long select_kth(const double2* w, const uint32_t* bits,
         const unsigned int dmask = (1u << nb) - 1u;
         for (int t = threadIdx.x; t < RADIX; t += IT) hist[t] = 0;
         __syncthreads();
-        for (int p = p0 + threadIdx.x; p < p1; p += IT) {
-            if (!((bits[p >> 5] >> (p & 31)) & 1u)) continue;
-            const double2 v = w[p];
-            const double m2 = v.x * v.x + v.y * v.y;
-            if (m2 == 0.0 || m2 < tau2) continue;
-            const unsigned long long k = key_of(m2);
-            if ((k & pmask) != prefix) continue;
-            atomicAdd(&hist[(unsigned int)(k >> sh) & dmask], 1u);
+        // WB positions per thread at a time, their loads issued together
+        for (int pb = p0 + threadIdx.x; pb < p1; pb += WB * IT) {
+            double2 vb[WB];
+#pragma unroll
+            for (int u = 0; u < WB; ++u) vb[u] = w[min(pb + u * IT, p1 - 1)];
+#pragma unroll
+            for (int u = 0; u < WB; ++u) {
+                const int p = pb + u * IT;
+                if (p >= p1 || !((bits[p >> 5] >> (p & 31)) & 1u)) continue;
+                const double m2 = vb[u].x * vb[u].x + vb[u].y * vb[u].y;
+                if (m2 == 0.0 || m2 < tau2) continue;
+                const unsigned long long k = key_of(m2);
+                if ((k & pmask) != prefix) continue;
+                atomicAdd(&hist[(unsigned int)(k >> sh) & dmask], 1u);
+            }
         }
         __syncthreads();
         // thread t owns the digits dmask - 8t - j, j = 0..7 (descending); the
@@ -516,12 +524,18 @@ __device__ int output_side(const double2* w, const uint32_t* bits, int p0, int p
     // more present entries than the staging arrays hold: keys from the window
     if (ss.on && tid == 0) ++ss.tph[6];
     int cnt = 0;
-    for (int pp = p0 + tid; pp < p1; pp += IT) {
-        if (!((bits[pp >> 5] >> (pp & 31)) & 1u)) continue;
-        const double2 v = w[pp];
-        const double m2 = v.x * v.x + v.y * v.y;
-        if (m2 == 0.0 || m2 < tau2) continue;
-        ++cnt;
+    for (int pb = p0 + tid; pb < p1; pb += WB * IT) {
+        double2 vb[WB];
+#pragma unroll
+        for (int u = 0; u < WB; ++u) vb[u] = w[min(pb + u * IT, p1 - 1)];
+#pragma unroll
+        for (int u = 0; u < WB; ++u) {
+            const int pp = pb + u * IT;
+            if (pp >= p1 || !((bits[pp >> 5] >> (pp & 31)) & 1u)) continue;
+            const double m2 = vb[u].x * vb[u].x + vb[u].y * vb[u].y;
+            if (m2 == 0.0 || m2 < tau2) continue;
+            ++cnt;
+        }
     }
     const int tot = block_sum(cnt, sbuf);
     const bool cap = tot > lfil;
@@ -531,13 +545,19 @@ __device__ int output_side(const double2* w, const uint32_t* bits, int p0, int p
     const int chunk = (p1 - p0 + IT - 1) / IT;
     const int c0 = p0 + tid * chunk, c1 = min(p1, c0 + chunk);
     int keep = 0, eq = 0;
-    for (int pp = c0; pp < c1; ++pp) {
-        if (!((bits[pp >> 5] >> (pp & 31)) & 1u)) continue;
-        const double2 v = w[pp];
-        const double m2 = v.x * v.x + v.y * v.y;
-        if (m2 == 0.0 || m2 < tau2) continue;
-        const unsigned long long key = key_of(m2);
-        if (!cap || key > K) ++keep; else if (key == K) ++eq;
+    for (int pb = c0; pb < c1; pb += WB) {
+        double2 vb[WB];
+#pragma unroll
+        for (int u = 0; u < WB; ++u) vb[u] = w[min(pb + u, c1 - 1)];
+#pragma unroll
+        for (int u = 0; u < WB; ++u) {
+            const int pp = pb + u;
+            if (pp >= c1 || !((bits[pp >> 5] >> (pp & 31)) & 1u)) continue;
+            const double m2 = vb[u].x * vb[u].x + vb[u].y * vb[u].y;
+            if (m2 == 0.0 || m2 < tau2) continue;
+            const unsigned long long key = key_of(m2);
+            if (!cap || key > K) ++keep; else if (key == K) ++eq;
+        }
     }
     int tmp;
     const int eq_before = block_scan(eq, &tmp, sbuf);
@@ -545,19 +565,26 @@ __device__ int output_side(const double2* w, const uint32_t* bits, int p0, int p
     int total = 0;
     const int out = block_scan(keep + take, &total, sbuf);
     int written = 0, e = 0;
-    for (int pp = c0; pp < c1; ++pp) {
-        if (!((bits[pp >> 5] >> (pp & 31)) & 1u)) continue;
-        const double2 v = w[pp];
-        const double m2 = v.x * v.x + v.y * v.y;
-        if (m2 == 0.0 || m2 < tau2) continue;
-        const unsigned long long key = key_of(m2);
-        bool kp = !cap || key > K;
-        if (cap && key == K) kp = e++ < take;
-        if (kp) {
-            if (check_finite && (!isfinite(v.x) || !isfinite(v.y))) *bad = true;
-            ocol[out + written] = (int32_t)(lo + pp);
-            oval[out + written] = v;
-            ++written;
+    for (int pb = c0; pb < c1; pb += WB) {
+        double2 vb[WB];
+#pragma unroll
+        for (int u = 0; u < WB; ++u) vb[u] = w[min(pb + u, c1 - 1)];
+#pragma unroll
+        for (int u = 0; u < WB; ++u) {
+            const int pp = pb + u;
+            if (pp >= c1 || !((bits[pp >> 5] >> (pp & 31)) & 1u)) continue;
+            const double2 v = vb[u];
+            const double m2 = v.x * v.x + v.y * v.y;
+            if (m2 == 0.0 || m2 < tau2) continue;
+            const unsigned long long key = key_of(m2);
+            bool kp = !cap || key > K;
+            if (cap && key == K) kp = e++ < take;
+            if (kp) {
+                if (check_finite && (!isfinite(v.x) || !isfinite(v.y))) *bad = true;
+                ocol[out + written] = (int32_t)(lo + pp);
+                oval[out + written] = v;
+                ++written;
+            }
         }
     }
     __syncthreads();
