@@ -232,11 +232,17 @@ __device__ unsigned long long select_kth(const double2* w, const uint32_t* bits,
         __syncthreads();
         const int d = __builtin_amdgcn_readfirstlane(sbuf[0]);
         const int acc = __builtin_amdgcn_readfirstlane(sbuf[1]);
+        const int in_d = __builtin_amdgcn_readfirstlane((int)hist[d]);
         __syncthreads();
         above += acc;
         need -= acc;
         prefix |= ((unsigned long long)d) << sh;
         pmask |= ((unsigned long long)dmask) << sh;
+        if (need == in_d && prefix != 0ull) {
+            // every key of the chosen digit range is kept (as in select_kth_lds)
+            *n_gt = lfil;
+            return prefix - 1ull;
+        }
     }
     *n_gt = above;
     return prefix;
