@@ -26,3 +26,14 @@ def test_cpu_baseline_times_the_oracle():
     # a sample that cannot finish is reported as an upper bound
     big = bench.cpu_baseline(W.batch_params()[:1], None, 1.0)
     assert big["bound"] == "upper" and abs(big["value"] - 1.0) < 1e-12 and big["cores"] >= 1
+
+
+def test_studies_command_line_needs_a_device():
+    """The Fig. 2/4/5 studies run through the device library; without a HIP
+    device the command line says so and exits with status 2."""
+    import torch
+    if torch.cuda.is_available():
+        return
+    r = subprocess.run([sys.executable, "-m", "paper_1411_4356_amd.studies", "rcm", "--nc", "2", "--nm", "4"],
+                       capture_output=True, text=True, timeout=300, cwd=ROOT)
+    assert r.returncode == 2 and "HIP device" in r.stderr
