@@ -175,10 +175,11 @@ __device__ inline int block_or(bool v, int* sor) {
 }
 
 // Radix select over the candidate keys of one triangle: returns the key K of
-// the lfil-th largest and, in *n_gt, how many keys exceed K.
-// Requires 1 <= lfil < number of candidates.  sbuf: 8 ints.
+// the lfil-th largest and, in *n_gt, how many keys exceed K, with *capped
+// true; with at most lfil candidates (counted by the first pass) it returns
+// at once with *capped false.  Requires lfil >= 1.  sbuf: 8 ints.
 __device__ unsigned long long select_kth(const double2* w, const uint32_t* bits, int p0, int p1, double tau2, int lfil,
-                                         int* n_gt, unsigned int* hist, int* sbuf) {
+                                         int* n_gt, unsigned int* hist, int* sbuf, bool* capped) {
     unsigned long long prefix = 0, pmask = 0;
     int need = lfil;   // rank (1-based) of the wanted key among those matching the prefix, from the top
     int above = 0;     // keys strictly greater than the prefix range, counted so far
@@ -217,6 +218,11 @@ __device__ unsigned long long select_kth(const double2* w, const uint32_t* bits,
         }
         int tot;
         const int before = block_scan(own, &tot, sbuf + 2);
+        // the first pass counts every candidate: at most lfil means no cap
+        if (shift == 64 - RADIX_BITS) {
+            *capped = tot > lfil;
+            if (!*capped) return 0ull;
+        }
         if (before < need && need <= before + own) {
             int acc = before;
 #pragma unroll
@@ -324,7 +330,7 @@ constexpr int RPT = 8;          // candidate rounds per group (strided by the bl
 // While a row is eliminated, the staging arrays hold the part of the dense
 // working row around the diagonal (WIN_N positions, the most updated ones):
 // its read-modify-writes stay in LDS instead of going to memory.
-constexpr int WIN_N = 3584;
+constexpr int WIN_N = 3840;
 
 struct SideShared {
     alignas(16) unsigned long long key[CAND_MAX];
@@ -529,25 +535,12 @@ __device__ int output_side(const double2* w, const uint32_t* bits, int p0, int p
     }
     // more present entries than the staging arrays hold: keys from the window
     if (ss.on && tid == 0) ++ss.tph[6];
-    int cnt = 0;
-    for (int pb = p0 + tid; pb < p1; pb += WB * IT) {
-        double2 vb[WB];
-#pragma unroll
-        for (int u = 0; u < WB; ++u) vb[u] = w[min(pb + u * IT, p1 - 1)];
-#pragma unroll
-        for (int u = 0; u < WB; ++u) {
-            const int pp = pb + u * IT;
-            if (pp >= p1 || !((bits[pp >> 5] >> (pp & 31)) & 1u)) continue;
-            const double m2 = vb[u].x * vb[u].x + vb[u].y * vb[u].y;
-            if (m2 == 0.0 || m2 < tau2) continue;
-            ++cnt;
-        }
-    }
-    const int tot = block_sum(cnt, sbuf);
-    const bool cap = tot > lfil;
-    unsigned long long K = 0ull;
+    // the select counts the candidates in its first pass (cap or not); lfil = 0
+    // keeps nothing: K above every key, no ties taken
+    bool cap = true;
+    unsigned long long K = ~0ull;
     int n_gt = 0;
-    if (cap) K = lfil > 0 ? select_kth(w, bits, p0, p1, tau2, lfil, &n_gt, hist, sbuf + 4) : ~0ull;
+    if (lfil > 0) K = select_kth(w, bits, p0, p1, tau2, lfil, &n_gt, hist, sbuf + 4, &cap);
     const int chunk = (p1 - p0 + IT - 1) / IT;
     const int c0 = p0 + tid * chunk, c1 = min(p1, c0 + chunk);
     int keep = 0, eq = 0;
